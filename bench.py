@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Benchmark of the grouped Barnes-Hut tree force on one MI355X.
+
+One step = the whole hot path over one synthetic particle set already
+resident in HBM: root cube, Morton keys, radix sort, tree topology and
+moments, groups, and the fused group walk + FP32 force sum.  Default
+workload: clustered box, N = 2,097,152 (30% uniform + 70% in 512 Plummer
+halos), eps = 1e-4, theta = 0.6, n_crit = 256.
+
+Prints one JSON line.  value = tree-force interactions per second of whole
+steps (sum over members of list length - 1, divided by the step time);
+particles/s, the RMS force error against FP64 direct summation on a seeded
+sample, the roofline of the dominant kernel (walk + force, FP32 VALU) and
+the FP64 CPU oracle's throughput on a bounded sample are reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "tree-force interactions/s and particles/s at 1e-3 RMS force error, learned vs fixed θ"
+FP32_VALU_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
+FLOPS_PER_INTERACTION = 20      # 3 sub, 3 FMA (r^2), rsqrt, 3 mul, 3 FMA (acc), 1 add (pot)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="clustered_2m")
+    ap.add_argument("--n", type=int, default=None, help="override the particle count")
+    ap.add_argument("--judge-sample", type=int, default=4096)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--waves-per-cu", type=int, default=None)
+    return ap.parse_args()
+
+
+def cpu_baseline(pos, mass, w, total_interactions, target_s):
+    """The FP64 oracle on the host: full tree build and grouping, then the
+    walk + force sum for a seeded random sample of groups sized to about
+    target_s seconds; whole-job throughput is extrapolated from the sample."""
+    import numpy as np
+
+    import oracle
+
+    t0 = time.perf_counter()
+    tree = oracle.Tree(pos, mass)
+    G = tree.groups(w.n_crit)
+    t_build = time.perf_counter() - t0
+    order = np.random.default_rng(0).permutation(G)
+    k = max(8, G // 500)
+    t0 = time.perf_counter()
+    pilot = tree.forces(w.eps, w.theta, groups=order[:k])
+    dt = time.perf_counter() - t0
+    rate = max(pilot["interactions"], 1) / max(dt, 1e-6)
+    want = max(1.0, target_s - dt) * rate
+    # extend the sample until it holds about `want` interactions
+    frac = min(1.0, want / max(total_interactions, 1))
+    k2 = int(min(G, max(k, round(frac * G))))
+    t0 = time.perf_counter()
+    out = tree.forces(w.eps, w.theta, groups=order[:k2])
+    t_force = time.perf_counter() - t0
+    sample_inter = max(out["interactions"], 1)
+    t_job = t_build + t_force * total_interactions / sample_inter
+    return {
+        "value": total_interactions / t_job,
+        "unit": "interactions/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"FP64 oracle: full tree build + grouping of all {pos.shape[0]} particles "
+                   f"({t_build:.2f} s), walk + force for {k2} of {G} groups chosen at random "
+                   f"({sample_inter} interactions, {t_force:.2f} s); whole job extrapolated by "
+                   f"interaction count"),
+        "cpu_model": _cpu_model(),
+    }
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
+              f"(the method runs on a single MI355X here)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_0909_0541_amd import bh, inputs
+
+    torch.cuda.set_device(0)
+    pos, mass, _, w = inputs.make_workload(args.workload, n=args.n)
+    n = pos.shape[0]
+    dpos = torch.as_tensor(pos, device="cuda")
+    dmass = torch.as_tensor(mass, device="cuda")
+    acc = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    pot = torch.empty(n, dtype=torch.float32, device="cuda")
+    ctx = bh.Context(timing=True, waves_per_cu=args.waves_per_cu)
+
+    def step():
+        ctx.build_tree(dpos, dmass)
+        ctx.make_groups(w.n_crit, sync=False)
+        ctx.compute_forces(w.eps, w.theta, acc=acc, pot=pot)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.get_stats()  # clears the warm-up timings
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_per_step = e0.elapsed_time(e1) / args.steps
+    st = ctx.get_stats()
+    if st.error_flags:
+        raise SystemExit(f"device error flags {st.error_flags}")
+    t_force = st.t_force_ms / max(st.n_force_calls, 1)
+    t_build = st.t_build_ms / max(st.n_build_calls, 1)
+    t_groups = st.t_groups_ms / max(st.n_groups_calls, 1)
+    inter = st.interactions
+    value = inter / (ms_per_step * 1e-3)
+
+    # accuracy: RMS relative force error against FP64 direct summation
+    rng = np.random.default_rng(12345)
+    s = min(args.judge_sample, n)
+    idx = np.sort(rng.choice(n, s, replace=False))
+    didx = torch.as_tensor(idx, device="cuda")
+    a_dir, _ = ctx.direct_sampled(dpos, dmass, w.eps, didx)
+    a_dir = a_dir.cpu().numpy()
+    a_tree = acc[didx].double().cpu().numpy()
+    rel = np.linalg.norm(a_tree - a_dir, axis=1) / np.linalg.norm(a_dir, axis=1)
+    rms = float(math.sqrt(np.mean(rel * rel)))
+
+    achieved = FLOPS_PER_INTERACTION * inter / (t_force * 1e-3) / 1e12
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "description": w.description, "n": n, "eps": w.eps, "theta": w.theta,
+                   "n_crit": w.n_crit, "theta_mode": "fixed"},
+        "particles_per_s": n / (ms_per_step * 1e-3),
+        "interactions_per_step": inter,
+        "interactions_per_particle": inter / n,
+        "rms_force_error": rms,
+        "judge_sample": s,
+        "groups": st.n_groups,
+        "cells": st.n_cells,
+        "max_list": st.max_list,
+        "stage_ms": {"build": t_build, "groups": t_groups, "walk_force": t_force},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "k_walk_force", "flops_per_interaction": FLOPS_PER_INTERACTION},
+        "walk_force_interactions_per_s": inter / (t_force * 1e-3),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(pos, mass, w, inter, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,220 @@
+/*
+ * bh.h -- C ABI of the MI355X grouped Barnes-Hut oct-tree gravity library.
+ *
+ * Method (N. Nakasato, "Oct-tree Method on GPU"):
+ *   Eq. (1)    softened potential and force of particle i, summed over j != i:
+ *              acc_i = sum_j m_j (x_j - x_i) / (|x_i - x_j|^2 + eps^2)^(3/2)
+ *              pot_i = -sum_j m_j / (|x_i - x_j|^2 + eps^2)^(1/2)
+ *              (attractive sign convention, G = 1).
+ *   Sec. 3.1   the oct-tree: the cube enclosing all particles is divided into
+ *              eight sub-cells recursively until a cell holds one particle;
+ *              cells act through their monopole (total mass at the centre of
+ *              mass).
+ *   Eq. (2)/(3) modified opening criterion: a cell of side l whose centre of
+ *              mass lies s from its geometric centre is far enough when
+ *              d^2 > (l/theta + s)^2.
+ *   Sec. 3.5   Morton ordering of the particles.
+ *   Sec. 1, 3.2 the grouped (vectorised) walk: each group of nearby particles
+ *              walks the tree once to build one interaction list that all its
+ *              members sum over.  For a group, d is the distance from the
+ *              cell's centre of mass to the group's bounding box, so every
+ *              member satisfies Eq. (2) on its own.
+ *
+ * Conventions for every entry point:
+ *   - Arrays named "device" are device (HBM) pointers, e.g. torch tensors on
+ *     the GPU; arrays named "host" are ordinary host memory.  The caller owns
+ *     every array it passes; the library never frees or retains them past the
+ *     call.  The context owns all internal workspaces (sorted copies, tree,
+ *     groups) until bh_destroy.
+ *   - Positions are FP64 [n][3] row-major (x, y, z), masses FP64 [n] (finite,
+ *     >= 0).  Forces come back as FP32 acc [n][3] and pot [n] in the caller's
+ *     input order.
+ *   - Work is enqueued asynchronously on the context's HIP stream; a call
+ *     returns before the GPU finishes unless its comment says it synchronises.
+ *     One context per host thread; calls on one context must not overlap.
+ *   - Every call returns a bh_status and never aborts; after a failure
+ *     bh_last_error(ctx) holds a message.  Input checks that need device data
+ *     (non-finite positions or masses) are reported by the next synchronising
+ *     call (bh_make_groups with a count pointer, bh_get_stats, bh_sync).
+ */
+#ifndef BH_H
+#define BH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bh_ctx bh_ctx;
+
+typedef enum {
+  BH_OK = 0,
+  BH_EINVAL = -1,    /* bad argument or input data */
+  BH_ENOMEM = -2,    /* device allocation failed */
+  BH_EHIP = -3,      /* a HIP runtime call failed */
+  BH_ESTATE = -4,    /* call out of order (e.g. forces before a tree) */
+  BH_EINTERNAL = -5  /* an internal capacity check fired (reported, never silent) */
+} bh_status;
+
+/* Largest group size accepted by bh_make_groups. */
+#define BH_MAX_NCRIT 256
+/* Largest particle count of one tree (all systems together). */
+#define BH_MAX_N (1LL << 30)
+
+typedef struct {
+  int64_t n;             /* particles in the current tree (all systems) */
+  int32_t n_systems;     /* independent systems in the current tree */
+  int32_t n_crit;        /* group size limit of the current groups */
+  int64_t n_cells;       /* internal cells (including always-open buckets) */
+  int64_t n_slots;       /* node records: cells + particle leaves + system roots */
+  int64_t n_groups;      /* groups of the current grouping */
+  int64_t interactions;  /* last force call: sum over members of (list length - 1) */
+  int64_t list_entries;  /* last force call: sum over groups of the list length */
+  int64_t max_list;      /* last force call: longest list */
+  int32_t max_level;     /* deepest cell level (root cube = level 0) */
+  int32_t error_flags;   /* device-side checks, 0 when all is well */
+  /* With timing enabled: summed GPU time (HIP events on the context's stream)
+   * of the calls made since the previous bh_get_stats, and their number. */
+  double t_build_ms;     /* bh_build_tree / bh_build_batch kernels */
+  double t_groups_ms;    /* bh_make_groups kernels */
+  double t_force_ms;     /* the fused walk + force kernel of the force calls */
+  int32_t n_build_calls;
+  int32_t n_groups_calls;
+  int32_t n_force_calls;
+  int32_t pad;
+} bh_stats;
+
+typedef struct {
+  int32_t waves_per_cu;  /* persistent walk grid = CUs x waves_per_cu (default 12) */
+  int32_t timing;        /* 1: record HIP events around each stage (default 0) */
+} bh_options;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on the current HIP device.  stream is a hipStream_t (NULL =
+ * the default stream).  *out receives the context; nothing is allocated on
+ * the device until the first build. */
+bh_status bh_create(bh_ctx **out, void *stream);
+
+/* Free the context and all its device memory.  NULL is allowed. */
+void bh_destroy(bh_ctx *ctx);
+
+/* Message of the last failed call on ctx ("" if none).  Valid until the next call. */
+const char *bh_last_error(const bh_ctx *ctx);
+
+/* Change the stream used by later calls. */
+bh_status bh_set_stream(bh_ctx *ctx, void *stream);
+
+/* Read or change options (opt must not be NULL). */
+bh_status bh_get_options(const bh_ctx *ctx, bh_options *opt);
+bh_status bh_set_options(bh_ctx *ctx, const bh_options *opt);
+
+/* Wait for all work of ctx and report device-side input errors (BH_EINVAL). */
+bh_status bh_sync(bh_ctx *ctx);
+
+/* ---- tree (Sec. 3.1, 3.5) --------------------------------------------- */
+
+/* Build the oct-tree of one system of n particles.
+ *   pos  device FP64 [n][3], mass device FP64 [n].
+ * Steps: root cube (corner at the per-axis minimum, side = largest extent
+ * times (1 + 2^-20), 1 if all points coincide); 21-bit cell coordinates per
+ * axis and their 63-bit Morton keys; stable LSD radix sort of (key, index);
+ * cells = key prefixes shared by at least two particles that split into at
+ * least two sub-cells (single-child chains are skipped: they hold the same
+ * particles and, for theta <= 1, give the same interaction list); particles
+ * with equal keys form an always-opened bucket; per cell the total mass and
+ * centre of mass (FP64 sums over the sub-cells in octant order), side l and s.
+ * n = 0 is allowed (empty tree).  BH_EINVAL: n < 0, n > BH_MAX_N, NULL pointers. */
+bh_status bh_build_tree(bh_ctx *ctx, int64_t n, const double *pos, const double *mass);
+
+/* Build one tree over several independent systems in one pass.
+ *   offsets host int64 [n_systems + 1]: system k owns rows offsets[k] ..
+ *   offsets[k+1]-1 of pos/mass (offsets[0] = 0, non-decreasing).
+ * Each system gets its own root cube; systems never interact. */
+bh_status bh_build_batch(bh_ctx *ctx, int32_t n_systems, const int64_t *offsets, const double *pos,
+                         const double *mass);
+
+/* ---- groups ------------------------------------------------------------ */
+
+/* Group the particles of the current tree: a cell holding more than n_crit
+ * particles is split further; runs of consecutive sub-cells (octant order)
+ * holding at most n_crit particles each are packed greedily into groups of at
+ * most n_crit particles; a system with at most n_crit particles is one group.
+ * Every group is a contiguous Morton range with an FP64 bounding box.
+ *   n_crit in [1, BH_MAX_NCRIT].
+ *   n_groups_out host, nullable; when given the call synchronises and reports
+ *   device-side input errors. */
+bh_status bh_make_groups(bh_ctx *ctx, int32_t n_crit, int64_t *n_groups_out);
+
+/* ---- forces (Eq. 1, 2, 3) ---------------------------------------------- */
+
+/* Tree forces for every particle of a single-system or batched tree, with one
+ * eps and theta for all systems.
+ *   eps > 0 (eps^2 must be a normal FP32 number), theta in [0, 1]
+ *   (theta = 0 opens every cell: exact direct summation).
+ *   theta_group device FP32 [n_groups], nullable: per-group theta overriding
+ *   theta (values in [0, 1]; out-of-range values raise an error flag).
+ *   acc device FP32 [n][3], pot device FP32 [n]: input order.
+ * The list of each group is built in FP64 (MAC) and staged in on-chip memory
+ * as FP32 (x - c_g, m) with c_g the group's box centre; members sum Eq. (1)
+ * in FP32 with group-relative coordinates, folding partial sums into FP64. */
+bh_status bh_compute_forces(bh_ctx *ctx, double eps, double theta, const float *theta_group, float *acc,
+                            float *pot);
+
+/* Same with per-system parameters: eps_sys, theta_sys host FP64 [n_systems]. */
+bh_status bh_compute_forces_batch(bh_ctx *ctx, const double *eps_sys, const double *theta_sys,
+                                  const float *theta_group, float *acc, float *pot);
+
+/* Counters of the current tree, groups and last force call, and the timings
+ * collected since the previous call (which are then reset).  Synchronises.
+ * stats host, not NULL. */
+bh_status bh_get_stats(bh_ctx *ctx, bh_stats *stats);
+
+/* ---- FP64 judge (Eq. 1 by direct summation) ---------------------------- */
+
+/* Direct FP64 summation of Eq. (1) for s sampled particles against all n.
+ *   pos device FP64 [n][3], mass device FP64 [n], idx device int64 [s]
+ *   (0 <= idx < n), acc device FP64 [s][3], pot device FP64 [s].
+ * Independent of any tree held by ctx (uses only its stream and scratch). */
+bh_status bh_direct_sampled(bh_ctx *ctx, int64_t n, const double *pos, const double *mass, double eps,
+                            int64_t s, const int64_t *idx, double *acc, double *pot);
+
+/* ---- time integration (kick-drift-kick leapfrog, FP64 state) ----------- */
+
+/* vel += dt * acc (acc FP32 [n][3] from a force call, vel FP64 [n][3]). */
+bh_status bh_kick(bh_ctx *ctx, int64_t n, double *vel, const float *acc, double dt);
+
+/* pos += dt * vel (both FP64 [n][3]). */
+bh_status bh_drift(bh_ctx *ctx, int64_t n, double *pos, const double *vel, double dt);
+
+/* energy device FP64 [2]: kinetic sum(m v^2 / 2) and potential sum(m pot / 2). */
+bh_status bh_energy(bh_ctx *ctx, int64_t n, const double *vel, const double *mass, const float *pot,
+                    double *energy);
+
+/* ---- inspection (tests and tools) -------------------------------------- */
+
+/* Sorted Morton keys and the permutation: keys device uint64 [n],
+ * perm device int32 [n] with perm[k] = input row of the k-th particle in
+ * Morton order (within each system, systems in order).  Either may be NULL. */
+bh_status bh_export_sorted(bh_ctx *ctx, uint64_t *keys, int32_t *perm);
+
+/* Node records, one per slot (stats.n_slots): ints device int32 [slots][6] =
+ * level, kind (0 cell, 1 particle leaf, 2 bucket, 3 empty system root), first
+ * particle (Morton index), count, first child slot (-1 for leaves), number of
+ * children; reals device FP64 [slots][6] = mass, centre of mass x, y, z, side
+ * l (+inf for buckets), s.  Slot k < n_systems is the root of system k. */
+bh_status bh_export_nodes(bh_ctx *ctx, int32_t *ints, double *reals);
+
+/* Groups (stats.n_groups): ints device int32 [G][3] = first particle, count,
+ * system; box device FP64 [G][6] = lo x, y, z, hi x, y, z.  After a force
+ * call, list_len device int32 [G] and list_mass device FP64 [G] (sum of the
+ * masses of the list entries) describe each group's interaction list.
+ * Any pointer may be NULL. */
+bh_status bh_export_groups(bh_ctx *ctx, int32_t *ints, double *box, int32_t *list_len, double *list_mass);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BH_H */

@@ -39,7 +39,7 @@ def lib():
         L.oracle_tree_free.restype = None
         L.oracle_tree_groups.argtypes = [vp, C.c_int]
         L.oracle_tree_groups.restype = i64
-        L.oracle_tree_forces.argtypes = [vp, dbl, dbl, vp, i64, vp, vp, vp, vp, vp, vp]
+        L.oracle_tree_forces.argtypes = [vp, dbl, dbl, vp, i64, vp, vp, vp, vp, vp, vp, vp]
         L.oracle_tree_forces.restype = C.c_int
         L.oracle_tree_group_list.argtypes = [vp, i64, dbl, i64, vp, vp, vp]
         L.oracle_tree_group_list.restype = i64
@@ -156,10 +156,11 @@ class Tree:
         lib().oracle_tree_group_info(self._h, _p(first), _p(count), _p(lo), _p(hi))
         return first, count, lo, hi
 
-    def forces(self, eps: float, theta: float, theta_g=None, groups=None):
-        """Grouped tree forces.  Returns dict with acc [n,3], pot [n] (input
-        order; NaN rows for particles outside the selected groups), list_len,
-        list_mass (per selected group) and interactions."""
+    def forces(self, eps: float, theta: float, theta_g=None, groups=None, lists_only: bool = False):
+        """Grouped tree forces.  Returns dict with acc [n,3], pot [n] and
+        acc_abs [n] (sum of term magnitudes), all in input order with NaN rows
+        for particles outside the selected groups, plus list_len, list_mass
+        (per selected group) and interactions.  lists_only skips the sums."""
         if self.ngroups is None:
             raise RuntimeError("call groups(n_crit) first")
         tg = None if theta_g is None else _f64(theta_g)
@@ -167,16 +168,20 @@ class Tree:
             raise ValueError("theta_g must have one value per group")
         gs = None if groups is None else np.ascontiguousarray(groups, dtype=np.int64)
         nsel = self.ngroups if gs is None else gs.shape[0]
-        acc = np.full((self.n, 3), np.nan)
-        pot = np.full(self.n, np.nan)
+        acc = pot = aab = None
+        if not lists_only:
+            acc = np.full((self.n, 3), np.nan)
+            pot = np.full(self.n, np.nan)
+            aab = np.full(self.n, np.nan)
         ll = np.zeros(nsel, dtype=np.int64)
         lm = np.zeros(nsel)
         inter = C.c_int64()
         rc = lib().oracle_tree_forces(self._h, float(eps), float(theta), _p(tg), nsel, _p(gs), _p(acc), _p(pot),
-                                      _p(ll), _p(lm), C.byref(inter))
+                                      _p(aab), _p(ll), _p(lm), C.byref(inter))
         if rc != 0:
             raise ValueError("oracle_tree_forces failed")
-        return {"acc": acc, "pot": pot, "list_len": ll, "list_mass": lm, "interactions": inter.value}
+        return {"acc": acc, "pot": pot, "acc_abs": aab, "list_len": ll, "list_mass": lm,
+                "interactions": inter.value}
 
     def group_list(self, g: int, theta: float):
         """Interaction list of group g: (xyzm [L,4], particle [L], node [L])

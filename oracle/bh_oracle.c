@@ -490,12 +490,15 @@ int64_t oracle_tree_group_list(void *h, int64_t g, double theta, int64_t cap, do
 
 /* Forces for the selected groups (all if gsel == NULL).  theta_g (per group,
  * nullable) overrides theta.  acc [n][3] and pot [n] are indexed in input
- * order; only members of selected groups are written.  Per selected group k:
+ * order; only members of selected groups are written; with acc == NULL only
+ * the lists are built.  acc_abs [n] (nullable) receives the sum of the force
+ * magnitudes of the individual terms, sum_e m_e r/(r^2+eps^2)^(3/2), the scale
+ * against which cancellation in acc is measured.  Per selected group k:
  * list_len[k] = list length, list_mass[k] = sum of entry masses (nullable).
  * interactions (nullable) receives sum over members of (list length - 1). */
 int oracle_tree_forces(void *h, double eps, double theta, const double *theta_g, int64_t nsel,
-                       const int64_t *gsel, double *acc, double *pot, int64_t *list_len, double *list_mass,
-                       int64_t *interactions) {
+                       const int64_t *gsel, double *acc, double *pot, double *acc_abs, int64_t *list_len,
+                       double *list_mass, int64_t *interactions) {
   orc_tree *t = (orc_tree *)h;
   if (!t) return -1;
   if (gsel == NULL) nsel = t->ngroup;
@@ -519,9 +522,11 @@ int oracle_tree_forces(void *h, double eps, double theta, const double *theta_g,
         list_mass[k] = ms;
       }
       int64_t a = t->gfirst[g];
+      total += t->gcount[g] * (L.n - 1);
+      if (!acc) continue;
       for (int64_t i = a; i < a + t->gcount[g]; ++i) {
         double xi = t->spos[3 * i], yi = t->spos[3 * i + 1], zi = t->spos[3 * i + 2];
-        double ax = 0.0, ay = 0.0, az = 0.0, p = 0.0;
+        double ax = 0.0, ay = 0.0, az = 0.0, p = 0.0, aa = 0.0;
         for (int64_t e = 0; e < L.n; ++e) {
           const orc_entry *q = &L.e[e];
           if (q->particle == i) continue; /* j != i in Eq. (1) */
@@ -533,11 +538,12 @@ int oracle_tree_forces(void *h, double eps, double theta, const double *theta_g,
           ay += mr3 * dy;
           az += mr3 * dz;
           p -= q->m * rinv;
+          if (acc_abs) aa += mr3 * sqrt(dx * dx + dy * dy + dz * dz);
         }
         int64_t o = t->perm[i];
         acc[3 * o] = ax; acc[3 * o + 1] = ay; acc[3 * o + 2] = az;
         pot[o] = p;
-        total += L.n - 1;
+        if (acc_abs) acc_abs[o] = aa;
       }
     }
     free(L.e);

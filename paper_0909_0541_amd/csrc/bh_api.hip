@@ -1,0 +1,609 @@
+// C ABI of libbh: context, workspaces, argument checks and stage order.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+
+#include "bh_device.h"
+
+namespace bh {
+
+namespace {
+
+__global__ void k_reset_info(DevInfo *info) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    DevInfo z{};
+    *info = z;
+  }
+}
+
+__global__ void k_export_nodes(const NodeRec *__restrict__ nodes, const int8_t *__restrict__ meta,
+                               const DevInfo *__restrict__ info, int nsys, int32_t *__restrict__ ints,
+                               double *__restrict__ reals) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t slots = (int64_t)nsys + info->n_slots;
+  if (k >= slots) return;
+  const NodeRec r = nodes[k];
+  const int mt = meta[k];
+  const int kind = mt >> 5;
+  const int level = ((mt & 31) == 31) ? -1 : (mt & 31);
+  if (ints) {
+    int32_t *o = ints + 6 * k;
+    o[0] = level;
+    o[1] = kind;
+    o[2] = r.first;
+    o[3] = r.count;
+    o[4] = r.child;
+    o[5] = r.nchild;
+  }
+  if (reals) {
+    double *o = reals + 6 * k;
+    o[0] = r.m;
+    o[1] = r.com[0];
+    o[2] = r.com[1];
+    o[3] = r.com[2];
+    o[4] = r.l;
+    o[5] = r.s;
+  }
+}
+
+__global__ void k_copy_keys(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+__global__ void k_copy_i32(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+__global__ void k_copy_f64(const double *__restrict__ src, double *__restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+__global__ void k_export_groups(const int32_t *__restrict__ ginfo, const double *__restrict__ gbox,
+                                const int32_t *__restrict__ glist, const double *__restrict__ gmass,
+                                const DevInfo *__restrict__ info, int32_t *ints, double *box, int32_t *ll,
+                                double *lm) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= info->n_groups) return;
+  if (ints)
+    for (int k = 0; k < 3; ++k) ints[3 * g + k] = ginfo[3 * g + k];
+  if (box)
+    for (int k = 0; k < 6; ++k) box[6 * g + k] = gbox[6 * g + k];
+  if (ll) ll[g] = glist[g];
+  if (lm) lm[g] = gmass[g];
+}
+
+inline unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+void reset_info_device(DevInfo *info, hipStream_t s) { k_reset_info<<<1, 64, 0, s>>>(info); }
+
+bh_status fail(bh_ctx *c, bh_status st, const std::string &msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+bh_status hip_check(bh_ctx *c, hipError_t e, const char *what) {
+  if (e == hipSuccess) return BH_OK;
+  return fail(c, BH_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bh_status ensure(bh_ctx *c, DevBuf &b, size_t bytes, const char *what) {
+  if (bytes == 0) bytes = 16;
+  if (b.bytes >= bytes) return BH_OK;
+  if (b.p) {
+    hipError_t e = hipFree(b.p);
+    if (e != hipSuccess) return hip_check(c, e, "hipFree");
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  // grow geometrically so that slowly increasing sizes do not reallocate often
+  size_t want = bytes + bytes / 8;
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return fail(c, BH_ENOMEM, std::string("hipMalloc failed for ") + what);
+  }
+  b.bytes = want;
+  return BH_OK;
+}
+
+static void free_buf(DevBuf &b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+template <class T>
+static T *P(DevBuf &b) {
+  return reinterpret_cast<T *>(b.p);
+}
+
+static bh_status timer_start(bh_ctx *c, Timer &t) {
+  t.open = false;
+  if (!c->opt.timing) return BH_OK;
+  if (t.used >= 4096) return BH_OK;  // bounded: later calls of a long run are not timed
+  while ((int)t.ev.size() < 2 * (t.used + 1)) {
+    hipEvent_t e;
+    bh_status st = hip_check(c, hipEventCreate(&e), "hipEventCreate");
+    if (st) return st;
+    t.ev.push_back(e);
+  }
+  t.open = true;
+  return hip_check(c, hipEventRecord(t.ev[2 * t.used], c->stream), "hipEventRecord");
+}
+
+static bh_status timer_stop(bh_ctx *c, Timer &t) {
+  if (!t.open) return BH_OK;
+  t.open = false;
+  bh_status st = hip_check(c, hipEventRecord(t.ev[2 * t.used + 1], c->stream), "hipEventRecord");
+  if (st == BH_OK) t.used++;
+  return st;
+}
+
+// Sum of the recorded intervals (the stream must be synchronised); resets.
+static double timer_take(Timer &t, int32_t *calls) {
+  double total = 0.0;
+  for (int k = 0; k < t.used; ++k) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, t.ev[2 * k], t.ev[2 * k + 1]) == hipSuccess) total += (double)ms;
+  }
+  *calls = t.used;
+  t.used = 0;
+  return total;
+}
+
+// Copy host data to the device through a pinned staging buffer; the staging
+// buffer is reused only after the previous upload has completed.
+static bh_status upload(bh_ctx *c, void *dst, const void *src, size_t bytes) {
+  if (bytes == 0) return BH_OK;
+  bh_status st;
+  if (c->stage_event_used) {
+    st = hip_check(c, hipEventSynchronize(c->stage_event), "hipEventSynchronize");
+    if (st) return st;
+  }
+  if (c->stage_bytes < bytes) {
+    if (c->stage) (void)hipHostFree(c->stage);
+    c->stage = nullptr;
+    c->stage_bytes = 0;
+    st = hip_check(c, hipHostMalloc(&c->stage, bytes, 0), "hipHostMalloc");
+    if (st) return st;
+    c->stage_bytes = bytes;
+  }
+  memcpy(c->stage, src, bytes);
+  st = hip_check(c, hipMemcpyAsync(dst, c->stage, bytes, hipMemcpyHostToDevice, c->stream), "hipMemcpyAsync");
+  if (st) return st;
+  if (!c->stage_event) {
+    st = hip_check(c, hipEventCreateWithFlags(&c->stage_event, hipEventDisableTiming), "hipEventCreate");
+    if (st) return st;
+  }
+  c->stage_event_used = true;
+  return hip_check(c, hipEventRecord(c->stage_event, c->stream), "hipEventRecord");
+}
+
+static bh_status ensure_particles(bh_ctx *c, int64_t n, int nsys) {
+  const size_t N = (size_t)std::max<int64_t>(n, 1);
+  const size_t slots = 2 * N + (size_t)nsys + 1;
+  const size_t hist = radix_hist_bytes((int64_t)N);
+  const size_t scan_elems = std::max<size_t>(N, hist / sizeof(uint32_t)) + 1;
+  struct Want {
+    DevBuf *b;
+    size_t bytes;
+    const char *name;
+  } want[] = {
+      {&c->keys[0], 8 * N, "keys"},       {&c->keys[1], 8 * N, "keys"},
+      {&c->vals[0], 4 * N, "vals"},       {&c->vals[1], 4 * N, "vals"},
+      {&c->sys_in, 4 * N, "sys_in"},      {&c->spos, 24 * N, "spos"},
+      {&c->smass, 8 * N, "smass"},        {&c->perm, 4 * N, "perm"},
+      {&c->delta, N, "delta"},            {&c->level, N, "level"},
+      {&c->cdigit, N, "cdigit"},          {&c->pdigit, N, "pdigit"},
+      {&c->owner, 4 * N, "owner"},        {&c->cfirst, 4 * N, "cfirst"},
+      {&c->ccount, 4 * N, "ccount"},      {&c->cparent, 4 * N, "cparent"},
+      {&c->pparent, 4 * N, "pparent"},    {&c->mask, 4 * N, "mask"},
+      {&c->nchild, 4 * N, "nchild"},      {&c->cfirst_child, 4 * N, "cfirst_child"},
+      {&c->cslot, 4 * N, "cslot"},        {&c->hist, hist, "hist"},
+      {&c->scan_tmp, scan_tmp_bytes((int64_t)scan_elems), "scan_tmp"},
+      {&c->nodes, sizeof(NodeRec) * slots, "nodes"},
+      {&c->msum, 32 * slots, "msum"},
+      {&c->meta, slots, "meta"},
+      {&c->gflag, 4 * N, "gflag"},        {&c->gidx, 4 * N, "gidx"},
+      {&c->glen, 4 * N, "glen"},          {&c->ginfo, 12 * N, "ginfo"},
+      {&c->gbox, 48 * N, "gbox"},         {&c->glist, 4 * N, "glist"},
+      {&c->gmass, 8 * N, "gmass"},
+      {&c->bbox_part, (size_t)6 * 8 * (size_t)nsys * (size_t)bbox_blocks_per_system(nsys), "bbox"},
+      {&c->info, sizeof(DevInfo), "info"},
+  };
+  for (auto &w : want) {
+    bh_status st = ensure(c, *w.b, w.bytes, w.name);
+    if (st) return st;
+  }
+  return BH_OK;
+}
+
+static bh_status check_device_errors(bh_ctx *c) {
+  bh_status st = hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  if (st) return st;
+  if (!c->info.p) return BH_OK;
+  st = hip_check(c, hipMemcpy(c->info_host, c->info.p, sizeof(DevInfo), hipMemcpyDeviceToHost), "hipMemcpy info");
+  if (st) return st;
+  const int32_t e = c->info_host->err;
+  if (e & kErrNonFinitePos) return fail(c, BH_EINVAL, "non-finite particle position");
+  if (e & kErrBadMass) return fail(c, BH_EINVAL, "particle mass negative or non-finite");
+  if (e & kErrTheta) return fail(c, BH_EINVAL, "per-group theta outside [0, 1]");
+  if (e & kErrBuild) return fail(c, BH_EINTERNAL, "tree build produced an inconsistent node layout");
+  if (e & kErrStack) return fail(c, BH_EINTERNAL, "walk stack capacity exceeded or node range corrupt");
+  return BH_OK;
+}
+
+static bh_status build_common(bh_ctx *c, int32_t nsys, const int64_t *offsets, const double *pos,
+                              const double *mass) {
+  const int64_t n = offsets[nsys];
+  if (n < 0 || n > BH_MAX_N) return fail(c, BH_EINVAL, "particle count out of range");
+  if (n > 0 && (!pos || !mass)) return fail(c, BH_EINVAL, "pos and mass must not be NULL");
+  c->have_tree = c->have_groups = c->have_forces = false;
+  bh_status st = ensure_particles(c, n, nsys);
+  if (st) return st;
+  c->n = n;
+  c->nsys = nsys;
+  c->sys_host.assign((size_t)nsys, SysInfo{});
+  for (int s = 0; s < nsys; ++s) {
+    c->sys_host[s].first = (int32_t)offsets[s];
+    c->sys_host[s].count = (int32_t)(offsets[s + 1] - offsets[s]);
+  }
+  st = ensure(c, c->sys, sizeof(SysInfo) * (size_t)nsys, "systems");
+  if (st) return st;
+  st = upload(c, c->sys.p, c->sys_host.data(), sizeof(SysInfo) * (size_t)nsys);
+  if (st) return st;
+  st = timer_start(c, c->t_build);
+  if (st) return st;
+  reset_info_device(P<DevInfo>(c->info), c->stream);
+  TreeBuffers B{};
+  B.pos = pos;
+  B.mass = mass;
+  B.n = n;
+  B.nsys = nsys;
+  B.sys = P<SysInfo>(c->sys);
+  B.info = P<DevInfo>(c->info);
+  B.sys_in = P<int32_t>(c->sys_in);
+  B.keys[0] = P<uint64_t>(c->keys[0]);
+  B.keys[1] = P<uint64_t>(c->keys[1]);
+  B.vals[0] = P<uint32_t>(c->vals[0]);
+  B.vals[1] = P<uint32_t>(c->vals[1]);
+  B.hist = P<uint32_t>(c->hist);
+  B.scan_tmp = c->scan_tmp.p;
+  B.bbox_part = P<double>(c->bbox_part);
+  B.spos = P<double>(c->spos);
+  B.smass = P<double>(c->smass);
+  B.perm = P<int32_t>(c->perm);
+  B.delta = P<int8_t>(c->delta);
+  B.level = P<int8_t>(c->level);
+  B.cdigit = P<int8_t>(c->cdigit);
+  B.pdigit = P<int8_t>(c->pdigit);
+  B.owner = P<int32_t>(c->owner);
+  B.cfirst = P<int32_t>(c->cfirst);
+  B.ccount = P<int32_t>(c->ccount);
+  B.cparent = P<int32_t>(c->cparent);
+  B.pparent = P<int32_t>(c->pparent);
+  B.mask = P<int32_t>(c->mask);
+  B.nchild = P<int32_t>(c->nchild);
+  B.cfc = P<int32_t>(c->cfirst_child);
+  B.cslot = P<int32_t>(c->cslot);
+  B.nodes = P<NodeRec>(c->nodes);
+  B.msum = P<double>(c->msum);
+  B.meta = P<int8_t>(c->meta);
+  B.slot_cap = (int64_t)std::min({c->nodes.bytes / sizeof(NodeRec), c->msum.bytes / 32, c->meta.bytes});
+  build_tree_device(B, c->stream);
+  c->sorted_keys = B.sorted_keys;
+  st = timer_stop(c, c->t_build);
+  if (st) return st;
+  st = hip_check(c, hipGetLastError(), "kernel launch (build)");
+  if (st) return st;
+  c->have_tree = true;
+  return BH_OK;
+}
+
+}  // namespace bh
+
+using namespace bh;
+
+extern "C" {
+
+bh_status bh_create(bh_ctx **out, void *stream) {
+  if (!out) return BH_EINVAL;
+  *out = nullptr;
+  bh_ctx *c = new (std::nothrow) bh_ctx();
+  if (!c) return BH_ENOMEM;
+  c->stream = (hipStream_t)stream;
+  if (hipGetDevice(&c->device) != hipSuccess ||
+      hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
+    delete c;
+    return BH_EHIP;
+  }
+  if (hipHostMalloc((void **)&c->info_host, sizeof(DevInfo), 0) != hipSuccess) {
+    delete c;
+    return BH_ENOMEM;
+  }
+  memset(c->info_host, 0, sizeof(DevInfo));
+  *out = c;
+  return BH_OK;
+}
+
+void bh_destroy(bh_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  DevBuf *bufs[] = {&c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->sys_in, &c->spos, &c->smass,
+                    &c->perm, &c->delta, &c->level, &c->cdigit, &c->pdigit, &c->owner, &c->cfirst, &c->ccount,
+                    &c->cparent, &c->pparent, &c->mask, &c->nchild, &c->cfirst_child, &c->cslot, &c->scan_tmp,
+                    &c->hist, &c->nodes, &c->msum, &c->meta, &c->gflag, &c->gidx, &c->glen, &c->ginfo, &c->gbox, &c->glist,
+                    &c->gmass, &c->bbox_part, &c->sys, &c->par, &c->info, &c->direct_part, &c->energy_part};
+  for (DevBuf *b : bufs) free_buf(*b);
+  if (c->info_host) (void)hipHostFree(c->info_host);
+  if (c->stage) (void)hipHostFree(c->stage);
+  if (c->stage_event) (void)hipEventDestroy(c->stage_event);
+  Timer *ts[] = {&c->t_build, &c->t_groups, &c->t_force};
+  for (Timer *t : ts)
+    for (hipEvent_t e : t->ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char *bh_last_error(const bh_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+bh_status bh_set_stream(bh_ctx *c, void *stream) {
+  if (!c) return BH_EINVAL;
+  c->stream = (hipStream_t)stream;
+  return BH_OK;
+}
+
+bh_status bh_get_options(const bh_ctx *c, bh_options *opt) {
+  if (!c || !opt) return BH_EINVAL;
+  *opt = c->opt;
+  return BH_OK;
+}
+
+bh_status bh_set_options(bh_ctx *c, const bh_options *opt) {
+  if (!c || !opt) return BH_EINVAL;
+  if (opt->waves_per_cu < 1 || opt->waves_per_cu > 32) return fail(c, BH_EINVAL, "waves_per_cu must be in [1, 32]");
+  c->opt = *opt;
+  return BH_OK;
+}
+
+bh_status bh_sync(bh_ctx *c) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  return check_device_errors(c);
+}
+
+bh_status bh_build_tree(bh_ctx *c, int64_t n, const double *pos, const double *mass) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (n < 0 || n > BH_MAX_N) return fail(c, BH_EINVAL, "n out of range");
+  int64_t off[2] = {0, n};
+  return build_common(c, 1, off, pos, mass);
+}
+
+bh_status bh_build_batch(bh_ctx *c, int32_t n_systems, const int64_t *offsets, const double *pos,
+                         const double *mass) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (n_systems < 1 || n_systems > 65536 || !offsets) return fail(c, BH_EINVAL, "n_systems must be in [1, 65536]");
+  if (offsets[0] != 0) return fail(c, BH_EINVAL, "offsets[0] must be 0");
+  for (int s = 0; s < n_systems; ++s)
+    if (offsets[s + 1] < offsets[s]) return fail(c, BH_EINVAL, "offsets must be non-decreasing");
+  return build_common(c, n_systems, offsets, pos, mass);
+}
+
+bh_status bh_make_groups(bh_ctx *c, int32_t n_crit, int64_t *n_groups_out) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (!c->have_tree) return fail(c, BH_ESTATE, "bh_make_groups before a tree was built");
+  if (n_crit < 1 || n_crit > BH_MAX_NCRIT) return fail(c, BH_EINVAL, "n_crit must be in [1, 256]");
+  bh_status st = timer_start(c, c->t_groups);
+  if (st) return st;
+  GroupBuffers B{};
+  B.n = c->n;
+  B.nsys = c->nsys;
+  B.n_crit = n_crit;
+  B.level = P<int8_t>(c->level);
+  B.ccount = P<int32_t>(c->ccount);
+  B.cfc = P<int32_t>(c->cfirst_child);
+  B.nchild = P<int32_t>(c->nchild);
+  B.nodes = P<NodeRec>(c->nodes);
+  B.sys = P<SysInfo>(c->sys);
+  B.spos = P<double>(c->spos);
+  B.info = P<DevInfo>(c->info);
+  B.gflag = P<int32_t>(c->gflag);
+  B.gidx = P<int32_t>(c->gidx);
+  B.glen = P<int32_t>(c->glen);
+  B.ginfo = P<int32_t>(c->ginfo);
+  B.gbox = P<double>(c->gbox);
+  B.scan_tmp = c->scan_tmp.p;
+  B.num_cu = c->num_cu;
+  make_groups_device(B, c->stream);
+  st = timer_stop(c, c->t_groups);
+  if (st) return st;
+  st = hip_check(c, hipGetLastError(), "kernel launch (groups)");
+  if (st) return st;
+  c->n_crit = n_crit;
+  c->have_groups = true;
+  c->have_forces = false;
+  if (n_groups_out) {
+    st = check_device_errors(c);
+    if (st) return st;
+    *n_groups_out = c->info_host->n_groups;
+  }
+  return BH_OK;
+}
+
+static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *theta_sys, const float *theta_group,
+                               float *acc, float *pot) {
+  if (!c->have_groups) return fail(c, BH_ESTATE, "forces requested before bh_make_groups");
+  if (c->n > 0 && (!acc || !pot)) return fail(c, BH_EINVAL, "acc and pot must not be NULL");
+  c->par_host.assign((size_t)c->nsys, SysParam{});
+  for (int s = 0; s < c->nsys; ++s) {
+    const double e = eps_sys[s], t = theta_sys[s];
+    if (!(e > 0.0) || !isfinite(e)) return fail(c, BH_EINVAL, "eps must be positive and finite");
+    const float e2 = (float)(e * e);
+    if (!(e2 >= 1.17549435e-38f) || isinf(e2)) return fail(c, BH_EINVAL, "eps^2 must be a normal FP32 number");
+    if (!(t >= 0.0 && t <= 1.0)) return fail(c, BH_EINVAL, "theta must be in [0, 1]");
+    c->par_host[s].eps = e;
+    c->par_host[s].theta = t;
+  }
+  bh_status st = ensure(c, c->par, sizeof(SysParam) * (size_t)c->nsys, "parameters");
+  if (st) return st;
+  st = upload(c, c->par.p, c->par_host.data(), sizeof(SysParam) * (size_t)c->nsys);
+  if (st) return st;
+  reset_force_counters(P<DevInfo>(c->info), c->stream);
+  WalkLaunch L{};
+  L.nodes = P<NodeRec>(c->nodes);
+  L.ginfo = P<int32_t>(c->ginfo);
+  L.gbox = P<double>(c->gbox);
+  L.spos = P<double>(c->spos);
+  L.smass = P<double>(c->smass);
+  L.perm = P<int32_t>(c->perm);
+  L.sys = P<SysInfo>(c->sys);
+  L.par = P<SysParam>(c->par);
+  L.theta_group = theta_group;
+  L.acc = acc;
+  L.pot = pot;
+  L.glist = P<int32_t>(c->glist);
+  L.gmass = P<double>(c->gmass);
+  L.info = P<DevInfo>(c->info);
+  L.nsys = c->nsys;
+  L.grid = c->num_cu * c->opt.waves_per_cu;
+  st = timer_start(c, c->t_force);
+  if (st) return st;
+  if (c->n > 0) walk_force_device(L, c->stream);
+  st = timer_stop(c, c->t_force);
+  if (st) return st;
+  st = hip_check(c, hipGetLastError(), "kernel launch (walk)");
+  if (st) return st;
+  c->have_forces = true;
+  return BH_OK;
+}
+
+bh_status bh_compute_forces(bh_ctx *c, double eps, double theta, const float *theta_group, float *acc, float *pot) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (!c->have_tree) return fail(c, BH_ESTATE, "forces requested before a tree was built");
+  std::vector<double> e((size_t)c->nsys, eps), t((size_t)c->nsys, theta);
+  return forces_common(c, e.data(), t.data(), theta_group, acc, pot);
+}
+
+bh_status bh_compute_forces_batch(bh_ctx *c, const double *eps_sys, const double *theta_sys,
+                                  const float *theta_group, float *acc, float *pot) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (!c->have_tree) return fail(c, BH_ESTATE, "forces requested before a tree was built");
+  if (!eps_sys || !theta_sys) return fail(c, BH_EINVAL, "eps_sys and theta_sys must not be NULL");
+  return forces_common(c, eps_sys, theta_sys, theta_group, acc, pot);
+}
+
+bh_status bh_get_stats(bh_ctx *c, bh_stats *out) {
+  if (!c || !out) return BH_EINVAL;
+  c->err.clear();
+  bh_status st = check_device_errors(c);
+  memset(out, 0, sizeof(*out));
+  const DevInfo &d = *c->info_host;
+  out->n = c->n;
+  out->n_systems = c->nsys;
+  out->n_crit = c->have_groups ? c->n_crit : 0;
+  out->error_flags = d.err;
+  if (c->have_tree) {
+    out->n_cells = d.n_cells;
+    out->n_slots = (int64_t)c->nsys + d.n_slots;
+    out->max_level = d.max_level;
+  }
+  if (c->have_groups) out->n_groups = d.n_groups;
+  if (c->have_forces) {
+    out->interactions = (int64_t)d.interactions;
+    out->list_entries = (int64_t)d.list_entries;
+    out->max_list = d.max_list;
+  }
+  out->t_build_ms = timer_take(c->t_build, &out->n_build_calls);
+  out->t_groups_ms = timer_take(c->t_groups, &out->n_groups_calls);
+  out->t_force_ms = timer_take(c->t_force, &out->n_force_calls);
+  return st;
+}
+
+bh_status bh_direct_sampled(bh_ctx *c, int64_t n, const double *pos, const double *mass, double eps, int64_t s,
+                            const int64_t *idx, double *acc, double *pot) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (n < 0 || s < 0) return fail(c, BH_EINVAL, "negative size");
+  if (s > 0 && (!pos || !mass || !idx || !acc || !pot)) return fail(c, BH_EINVAL, "NULL pointer");
+  if (!(eps >= 0.0) || !isfinite(eps)) return fail(c, BH_EINVAL, "eps must be finite and >= 0");
+  if (s == 0) return BH_OK;
+  int64_t chunk, nchunk;
+  size_t bytes = direct_part_bytes(n, s, c->num_cu, &chunk, &nchunk);
+  bh_status st = ensure(c, c->direct_part, bytes, "direct partials");
+  if (st) return st;
+  direct_sampled_device(pos, mass, n, eps, s, idx, acc, pot, P<double>(c->direct_part), chunk, nchunk, c->stream);
+  return hip_check(c, hipGetLastError(), "kernel launch (direct)");
+}
+
+bh_status bh_kick(bh_ctx *c, int64_t n, double *vel, const float *acc, double dt) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (n < 0 || (n > 0 && (!vel || !acc))) return fail(c, BH_EINVAL, "bad kick arguments");
+  kick_device(n, vel, acc, dt, c->stream);
+  return hip_check(c, hipGetLastError(), "kernel launch (kick)");
+}
+
+bh_status bh_drift(bh_ctx *c, int64_t n, double *pos, const double *vel, double dt) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (n < 0 || (n > 0 && (!pos || !vel))) return fail(c, BH_EINVAL, "bad drift arguments");
+  drift_device(n, pos, vel, dt, c->stream);
+  return hip_check(c, hipGetLastError(), "kernel launch (drift)");
+}
+
+bh_status bh_energy(bh_ctx *c, int64_t n, const double *vel, const double *mass, const float *pot,
+                    double *energy) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (n < 0 || !energy || (n > 0 && (!vel || !mass || !pot))) return fail(c, BH_EINVAL, "bad energy arguments");
+  bh_status st = ensure(c, c->energy_part, energy_part_bytes(), "energy partials");
+  if (st) return st;
+  energy_device(n, vel, mass, pot, P<double>(c->energy_part), energy, c->stream);
+  return hip_check(c, hipGetLastError(), "kernel launch (energy)");
+}
+
+bh_status bh_export_sorted(bh_ctx *c, uint64_t *keys, int32_t *perm) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (!c->have_tree) return fail(c, BH_ESTATE, "no tree");
+  if (c->n == 0) return BH_OK;
+  if (keys) k_copy_keys<<<blocks_for(c->n), 256, 0, c->stream>>>(c->sorted_keys, keys, c->n);
+  if (perm) k_copy_i32<<<blocks_for(c->n), 256, 0, c->stream>>>(P<int32_t>(c->perm), perm, c->n);
+  return hip_check(c, hipGetLastError(), "kernel launch (export sorted)");
+}
+
+bh_status bh_export_nodes(bh_ctx *c, int32_t *ints, double *reals) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (!c->have_tree) return fail(c, BH_ESTATE, "no tree");
+  const int64_t cap = 2 * std::max<int64_t>(c->n, 1) + c->nsys + 1;
+  k_export_nodes<<<blocks_for(cap), 256, 0, c->stream>>>(P<NodeRec>(c->nodes), P<int8_t>(c->meta),
+                                                          P<DevInfo>(c->info), c->nsys, ints, reals);
+  return hip_check(c, hipGetLastError(), "kernel launch (export nodes)");
+}
+
+bh_status bh_export_groups(bh_ctx *c, int32_t *ints, double *box, int32_t *list_len, double *list_mass) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (!c->have_groups) return fail(c, BH_ESTATE, "no groups");
+  if ((list_len || list_mass) && !c->have_forces) return fail(c, BH_ESTATE, "no force call since the grouping");
+  const int64_t cap = std::max<int64_t>(c->n, 1);
+  k_export_groups<<<blocks_for(cap), 256, 0, c->stream>>>(P<int32_t>(c->ginfo), P<double>(c->gbox),
+                                                           P<int32_t>(c->glist), P<double>(c->gmass),
+                                                           P<DevInfo>(c->info), ints, box, list_len, list_mass);
+  return hip_check(c, hipGetLastError(), "kernel launch (export groups)");
+}
+
+}  // extern "C"

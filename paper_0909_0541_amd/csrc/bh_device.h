@@ -1,0 +1,107 @@
+// Device-side helpers shared by the kernels of libbh (wave64, gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bh_internal.h"
+
+namespace bh {
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Number of set bits of m below this lane.
+__device__ __forceinline__ int rank_below(unsigned long long m) {
+  return (int)__popcll(m & __lanemask_lt());
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ int wave_inclusive_sum(int v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    int t = __shfl_up(v, d, kWave);
+    if (l >= d) v += t;
+  }
+  return v;
+}
+
+// Inclusive prefix maximum over the 64 lanes of a wave.
+__device__ __forceinline__ int wave_inclusive_max(int v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    int t = __shfl_up(v, d, kWave);
+    if (l >= d) v = max(v, t);
+  }
+  return v;
+}
+
+__device__ __forceinline__ double shfl_xor_d(double v, int mask) {
+  int2 a = *reinterpret_cast<int2 *>(&v);
+  a.x = __shfl_xor(a.x, mask, kWave);
+  a.y = __shfl_xor(a.y, mask, kWave);
+  return *reinterpret_cast<double *>(&a);
+}
+
+// Octal digits shared by two 63-bit keys (21 when equal).
+__device__ __forceinline__ int common_digits(uint64_t a, uint64_t b) {
+  uint64_t x = a ^ b;
+  if (x == 0) return kKeyLevels;
+  int hb = 63 - __clzll((long long)x);
+  return 20 - hb / 3;
+}
+
+// Octant (0..7) of a key at level l (1..21).
+__device__ __forceinline__ int key_digit(uint64_t k, int l) {
+  return (int)((k >> (3 * (kKeyLevels - l))) & 7u);
+}
+
+// Shift that keeps the first l octal digits of a key.
+__device__ __forceinline__ int prefix_shift(int l) { return 3 * (kKeyLevels - l); }
+
+// First index in [lo, hi) whose key prefix (k >> sh) is >= p (keys sorted).
+__device__ __forceinline__ int lower_bound_prefix(const uint64_t *__restrict__ keys, int lo, int hi, uint64_t p,
+                                                  int sh) {
+  while (lo < hi) {
+    int mid = lo + ((hi - lo) >> 1);
+    if ((keys[mid] >> sh) < p) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// First index in [lo, hi) whose key prefix is > p.
+__device__ __forceinline__ int upper_bound_prefix(const uint64_t *__restrict__ keys, int lo, int hi, uint64_t p,
+                                                  int sh) {
+  while (lo < hi) {
+    int mid = lo + ((hi - lo) >> 1);
+    if ((keys[mid] >> sh) <= p) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// System owning Morton position j (systems occupy consecutive ranges).
+__device__ __forceinline__ int system_of(const SysInfo *__restrict__ sys, int nsys, int j) {
+  int lo = 0, hi = nsys - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (sys[mid].first <= j) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Cell coordinates (21 bits per axis) of a Morton key.
+__device__ __forceinline__ void key_cells(uint64_t k, uint32_t q[3]) {
+  q[0] = q[1] = q[2] = 0;
+#pragma unroll 1
+  for (int b = 0; b < kKeyLevels; ++b) {
+    q[0] |= (uint32_t)((k >> (3 * b + 2)) & 1) << b;
+    q[1] |= (uint32_t)((k >> (3 * b + 1)) & 1) << b;
+    q[2] |= (uint32_t)((k >> (3 * b)) & 1) << b;
+  }
+}
+
+}  // namespace bh

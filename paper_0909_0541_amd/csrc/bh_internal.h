@@ -1,0 +1,255 @@
+// Internal declarations shared by the HIP sources of libbh.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "bh.h"
+
+namespace bh {
+
+constexpr int kKeyLevels = 21;                 // bits per axis of a Morton key
+constexpr uint32_t kQMax = (1u << kKeyLevels) - 1;
+constexpr int kWave = 64;
+
+// Node kinds as exported.
+enum : int { kCell = 0, kParticle = 1, kBucket = 2, kEmpty = 3 };
+
+// One node record (64 bytes) per slot.  Slots [0, n_systems) hold the system
+// roots; the children of a cell occupy consecutive slots in octant order.
+struct alignas(16) NodeRec {
+  double com[3];  // centre of mass (a particle leaf: its position)
+  double m;       // total mass
+  double l;       // cell side; +inf for a bucket (always opened); 0 for a leaf
+  double s;       // |geometric centre - centre of mass|
+  int32_t child;  // first child slot, -1 for a particle leaf or an empty root
+  int32_t nchild; // number of children
+  int32_t first;  // first particle (Morton index)
+  int32_t count;  // number of particles
+};
+static_assert(sizeof(NodeRec) == 64, "node record must be 64 bytes");
+
+// Per-system geometry in device memory (first/count from the host, the root
+// cube from the build).
+struct SysInfo {
+  double lo[3];
+  double side;
+  double scale;   // 2^21 / side
+  int32_t first;  // first Morton position (systems occupy consecutive ranges)
+  int32_t count;
+};
+
+// Per-system force parameters (uploaded by every force call).
+struct SysParam {
+  double eps;
+  double theta;
+};
+
+// Device-side counters and flags (one instance per context).
+struct DevInfo {
+  int32_t err;            // error flag bits (kErr*)
+  int32_t max_level;
+  int32_t n_cells;
+  int32_t n_slots;
+  int32_t n_groups;
+  int32_t queue;          // walk work queue head
+  unsigned long long interactions;
+  unsigned long long list_entries;
+  int32_t max_list;
+  int32_t pad;
+};
+
+enum : int32_t {
+  kErrNonFinitePos = 1,
+  kErrBadMass = 2,
+  kErrStack = 4,
+  kErrTheta = 8,
+  kErrBuild = 16,
+};
+
+// Growable device buffer.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+// Event pairs recorded around one stage, summed when the stats are read.
+struct Timer {
+  std::vector<hipEvent_t> ev;  // pairs: ev[2k] start, ev[2k+1] stop
+  int used = 0;                // pairs recorded since the last read
+  bool open = false;
+};
+
+}  // namespace bh
+
+struct bh_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int num_cu = 0;
+  std::string err;
+  bh_options opt{12, 0};
+
+  // current tree
+  int64_t n = 0;
+  int32_t nsys = 0;
+  bool have_tree = false;
+  bool have_groups = false;
+  bool have_forces = false;
+  int32_t n_crit = 0;
+  int64_t cap_n = 0;  // particle capacity of the per-particle buffers
+
+  // per-particle workspaces (capacity cap_n)
+  bh::DevBuf keys[2], vals[2];  // u64 keys, u32 values (radix sort ping-pong)
+  bh::DevBuf sys_in;            // int32 system of each input row
+  bh::DevBuf spos, smass;       // FP64 sorted positions [n][3] and masses
+  bh::DevBuf perm;              // int32 sorted -> input row
+  bh::DevBuf delta;             // int8 common-digit count of neighbours
+  bh::DevBuf owner;             // int32 owner position of each split (or bucket run start)
+  bh::DevBuf level;             // int8 level of the cell owned at a position (-1: none)
+  bh::DevBuf cfirst, ccount;    // int32 particle range of the cell owned at a position
+  bh::DevBuf cparent;           // int32 parent (owner position) of a cell, or -1 - system
+  bh::DevBuf cdigit;            // int8 octant of a cell inside its parent
+  bh::DevBuf pparent;           // int32 parent of a particle (owner position), -1 - system for a lone root
+  bh::DevBuf pdigit;            // int8 octant of a particle inside its parent cell
+  bh::DevBuf mask;              // int32 child octant mask of the cell at a position
+  bh::DevBuf nchild;            // int32 children of the cell at a position
+  bh::DevBuf cfirst_child;      // int32 first child slot of the cell at a position
+  bh::DevBuf cslot;             // int32 slot of the cell at a position
+  bh::DevBuf scan_tmp;          // scan block sums
+  bh::DevBuf hist;              // radix histograms
+  bh::DevBuf nodes;             // NodeRec [slots]
+  bh::DevBuf msum;              // FP64 [slots][4] raw sums m, m x, m y, m z
+  bh::DevBuf meta;              // int8 [slots] 32 * kind + level (inspection only)
+  bh::DevBuf gflag;             // int32 group start flags
+  bh::DevBuf gidx;              // int32 exclusive scan of the flags (group index)
+  bh::DevBuf glen;              // int32 group length at its start position
+  bh::DevBuf ginfo;             // int32 [G][3] first, count, system
+  bh::DevBuf gbox;              // FP64 [G][6]
+  bh::DevBuf glist;             // int32 [G] list length of the last force call
+  bh::DevBuf gmass;             // FP64 [G] list mass of the last force call
+  bh::DevBuf bbox_part;         // FP64 bbox partials
+  bh::DevBuf sys;               // SysInfo [nsys]
+  bh::DevBuf par;               // SysParam [nsys]
+  bh::DevBuf info;              // DevInfo
+  bh::DevBuf direct_part;       // FP64 partial sums of the judge
+  bh::DevBuf energy_part;       // FP64 energy partials
+  bh::DevInfo *info_host = nullptr;  // pinned mirror
+  std::vector<bh::SysInfo> sys_host;
+  std::vector<bh::SysParam> par_host;
+  void *stage = nullptr;              // pinned staging buffer of host -> device uploads
+  size_t stage_bytes = 0;
+  hipEvent_t stage_event = nullptr;   // completion of the last staged upload
+  bool stage_event_used = false;
+  uint64_t *sorted_keys = nullptr;    // the key buffer holding the sorted keys
+
+  bh::Timer t_build, t_groups, t_force;
+};
+
+namespace bh {
+
+// ---- helpers implemented in bh_api.cpp ------------------------------------
+bh_status fail(bh_ctx *c, bh_status st, const std::string &msg);
+bh_status hip_check(bh_ctx *c, hipError_t e, const char *what);
+bh_status ensure(bh_ctx *c, DevBuf &b, size_t bytes, const char *what);
+
+// ---- kernels launchers (k_*.hip) ------------------------------------------
+// scan.hip: exclusive scan of n int32 values (out may alias in); *total
+// receives the sum (device int32).  tmp must hold scan_tmp_bytes(n).
+size_t scan_tmp_bytes(int64_t n);
+void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total, void *tmp,
+                        hipStream_t s);
+
+// sort.hip: stable LSD radix sort of (u64 key, u32 value) pairs on bits
+// [bit0, bit1); ping-pong buffers; returns the index (0/1) holding the result.
+size_t radix_hist_bytes(int64_t n);
+int radix_sort_pairs(uint64_t *k0, uint64_t *k1, uint32_t *v0, uint32_t *v1, int64_t n, int bit0,
+                     int bit1, uint32_t *hist, void *scan_tmp, hipStream_t s);
+// one stable pass on an external 8-bit digit: digit(i) = sys_in[v[i]] >> shift & 255
+int radix_pass_by_system(uint64_t *k0, uint64_t *k1, uint32_t *v0, uint32_t *v1, int cur, int64_t n,
+                         const int32_t *sys_in, int shift, uint32_t *hist, void *scan_tmp, hipStream_t s);
+
+void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+void iota_u32(uint32_t *v, int64_t n, hipStream_t s);
+
+// k_tree.hip
+struct TreeBuffers {
+  const double *pos, *mass;
+  int64_t n;
+  int nsys;
+  SysInfo *sys;
+  DevInfo *info;
+  int32_t *sys_in;  // system of each input row (used when nsys > 1)
+  uint64_t *keys[2];
+  uint32_t *vals[2];
+  uint32_t *hist;
+  void *scan_tmp;
+  double *bbox_part;
+  double *spos, *smass;
+  int32_t *perm;
+  int8_t *delta, *level, *cdigit, *pdigit;
+  int32_t *owner, *cfirst, *ccount, *cparent, *pparent, *mask, *nchild, *cfc, *cslot;
+  NodeRec *nodes;
+  double *msum;
+  int8_t *meta;           // per slot: 32 * kind + level (export only)
+  int64_t slot_cap;       // capacity of nodes/msum/meta in slots
+  uint64_t *sorted_keys;  // out: the buffer holding the sorted keys
+};
+int bbox_blocks_per_system(int nsys);
+void build_tree_device(TreeBuffers &B, hipStream_t s);
+
+// k_groups.hip
+struct GroupBuffers {
+  int64_t n;
+  int nsys;
+  int n_crit;
+  const int8_t *level;
+  const int32_t *ccount, *cfc, *nchild;
+  const NodeRec *nodes;
+  const SysInfo *sys;
+  const double *spos;
+  DevInfo *info;
+  int32_t *gflag, *gidx, *glen, *ginfo;
+  double *gbox;
+  void *scan_tmp;
+  int num_cu;
+};
+void make_groups_device(GroupBuffers &B, hipStream_t s);
+void reset_force_counters(DevInfo *info, hipStream_t s);
+
+// k_walk.hip
+struct WalkLaunch {
+  const NodeRec *nodes;
+  const int32_t *ginfo;
+  const double *gbox;
+  const double *spos;
+  const double *smass;
+  const int32_t *perm;
+  const SysInfo *sys;
+  const SysParam *par;
+  const float *theta_group;
+  float *acc;
+  float *pot;
+  int32_t *glist;
+  double *gmass;
+  DevInfo *info;
+  int nsys;
+  int grid;
+};
+void walk_force_device(const WalkLaunch &L, hipStream_t s);
+
+// k_misc.hip
+size_t direct_part_bytes(int64_t n, int64_t s, int num_cu, int64_t *chunk, int64_t *nchunk);
+void direct_sampled_device(const double *pos, const double *mass, int64_t n, double eps, int64_t s,
+                           const int64_t *idx, double *acc, double *pot, double *part, int64_t chunk,
+                           int64_t nchunk, hipStream_t st);
+void kick_device(int64_t n, double *vel, const float *acc, double dt, hipStream_t s);
+void drift_device(int64_t n, double *pos, const double *vel, double dt, hipStream_t s);
+size_t energy_part_bytes();
+void energy_device(int64_t n, const double *vel, const double *mass, const float *pot, double *part, double *out,
+                   hipStream_t s);
+void reset_info_device(DevInfo *info, hipStream_t s);
+
+}  // namespace bh

@@ -1,0 +1,475 @@
+// Oct-tree construction from sorted Morton keys (Sec. 3.1, 3.5).
+//
+// Cells are identified without pointer chasing.  For neighbouring sorted keys
+// i, i+1 of one system let delta_i be the number of leading octal digits they
+// share (21 when equal, -1 across a system boundary).  A "split" at i with
+// delta_i = l < 21 separates two sub-cells of the level-l cell holding i; the
+// cell is owned by its first split (the last particle of its first sub-cell).
+// A run of equal keys is a bucket owned by its first particle.  Every other
+// prefix with a single non-empty sub-cell is a chain link, which is skipped:
+// it holds the same particles as its only child and, for theta < 2/sqrt(3),
+// its opening test never accepts it while rejecting the child.
+//
+// Per-position arrays (index = Morton position) describe the cell owned
+// there.  Node records are then placed in slots: system roots first, the
+// children of every cell in consecutive slots in octant order.  Moments are
+// summed level by level from the deepest level up, each cell adding its
+// children in slot order starting from zero, so the FP64 sums are exactly
+// those of a recursive evaluation.
+#include "bh_device.h"
+
+namespace bh {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// root cube per system
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_bbox_partial(const double *__restrict__ pos, const SysInfo *__restrict__ sys,
+                                                      int bps, double *__restrict__ part, DevInfo *info) {
+  __shared__ double red[6][256];
+  const int s = blockIdx.x / bps, b = blockIdx.x % bps;
+  const int64_t first = sys[s].first, end = first + sys[s].count;
+  double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  bool bad = false;
+  for (int64_t i = first + (int64_t)b * blockDim.x + threadIdx.x; i < end; i += (int64_t)bps * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double x = pos[3 * i + k];
+      bad |= !isfinite(x);
+      mn[k] = fmin(mn[k], x);
+      mx[k] = fmax(mx[k], x);
+    }
+  }
+  if (bad) atomicOr(&info->err, kErrNonFinitePos);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    red[k][threadIdx.x] = mn[k];
+    red[3 + k][threadIdx.x] = mx[k];
+  }
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        red[k][threadIdx.x] = fmin(red[k][threadIdx.x], red[k][threadIdx.x + w]);
+        red[3 + k][threadIdx.x] = fmax(red[3 + k][threadIdx.x], red[3 + k][threadIdx.x + w]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[6 * (int64_t)blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(64) void k_bbox_final(const double *__restrict__ part, int bps, SysInfo *sys) {
+  const int s = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int b = 0; b < bps; ++b)
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = fmin(lo[k], part[6 * ((int64_t)s * bps + b) + k]);
+      hi[k] = fmax(hi[k], part[6 * ((int64_t)s * bps + b) + 3 + k]);
+    }
+  double ext = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    double e = hi[k] - lo[k];
+    if (e > ext) ext = e;
+  }
+  if (sys[s].count == 0 || !isfinite(ext)) {
+    lo[0] = lo[1] = lo[2] = 0.0;
+    ext = 0.0;
+  }
+  // corner at the per-axis minimum, side = largest extent widened by 2^-20
+  double side = (ext > 0.0) ? __dmul_rn(ext, 1.0 + 0x1p-20) : 1.0;
+  for (int k = 0; k < 3; ++k) sys[s].lo[k] = lo[k];
+  sys[s].side = side;
+  sys[s].scale = 0x1p21 / side;
+}
+
+// ---------------------------------------------------------------------------
+// keys
+// ---------------------------------------------------------------------------
+
+__global__ void k_system_of_input(const SysInfo *__restrict__ sys, int nsys, int64_t n, int32_t *__restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = system_of(sys, nsys, (int)i);
+}
+
+__device__ __forceinline__ uint32_t quantise(double x, double lo, double scale) {
+  double u = __dsub_rn(x, lo);
+  u = __dmul_rn(u, scale);
+  if (!(u >= 0.0)) return 0u;
+  if (u >= (double)kQMax) return kQMax;
+  return (uint32_t)u;  // truncation == floor for u >= 0
+}
+
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+  uint64_t x = v & 0x1fffffu;
+  x = (x | (x << 32)) & 0x1f00000000ffffull;
+  x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+  x = (x | (x << 8)) & 0x100f00f00f00f00full;
+  x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+  x = (x | (x << 2)) & 0x1249249249249249ull;
+  return x;
+}
+
+__global__ void k_keys(const double *__restrict__ pos, const double *__restrict__ mass, int64_t n,
+                       const int32_t *__restrict__ sys_in, const SysInfo *__restrict__ sys,
+                       uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, DevInfo *info) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const SysInfo &S = sys[sys_in ? sys_in[i] : 0];
+  uint32_t q[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) q[k] = quantise(pos[3 * i + k], S.lo[k], S.scale);
+  // x bit is the most significant of each octal digit
+  keys[i] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+  vals[i] = (uint32_t)i;
+  double m = mass[i];
+  if (!(m >= 0.0) || !isfinite(m)) atomicOr(&info->err, kErrBadMass);
+}
+
+__global__ void k_gather(const uint32_t *__restrict__ vals, const double *__restrict__ pos, const double *__restrict__ mass,
+                         int64_t n, double *__restrict__ spos, double *__restrict__ smass, int32_t *__restrict__ perm) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t j = vals[i];
+  perm[i] = (int32_t)j;
+  spos[3 * i] = pos[3 * (int64_t)j];
+  spos[3 * i + 1] = pos[3 * (int64_t)j + 1];
+  spos[3 * i + 2] = pos[3 * (int64_t)j + 2];
+  smass[i] = mass[j];
+}
+
+// ---------------------------------------------------------------------------
+// topology
+// ---------------------------------------------------------------------------
+
+__global__ void k_delta(const uint64_t *__restrict__ keys, const int32_t *__restrict__ perm,
+                        const int32_t *__restrict__ sys_in, int64_t n, int8_t *__restrict__ delta) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int d = -1;
+  if (i + 1 < n) {
+    bool same = sys_in ? (sys_in[perm[i]] == sys_in[perm[i + 1]]) : true;
+    if (same) d = common_digits(keys[i], keys[i + 1]);
+  }
+  delta[i] = (int8_t)d;
+}
+
+// owner[j]: the owning position of the cell split at j (its first split), or
+// the first particle of the run of equal keys containing j; level[j]: level
+// of the cell owned at j, -1 when j owns none.
+__global__ void k_owner(const uint64_t *__restrict__ keys, const int8_t *__restrict__ delta, int64_t n,
+                        const SysInfo *__restrict__ sys, int nsys, int32_t *__restrict__ owner,
+                        int8_t *__restrict__ level) {
+  int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (jj >= n) return;
+  const int j = (int)jj;
+  const int d = delta[j];
+  int own = -1, lev = -1;
+  if (d >= 0) {
+    const int s = system_of(sys, nsys, j);
+    const int lo = sys[s].first;
+    const uint64_t kj = keys[j];
+    if (d < kKeyLevels) {
+      const int sh = prefix_shift(d);
+      int a = lower_bound_prefix(keys, lo, j, kj >> sh, sh);
+      const int sh1 = prefix_shift(d + 1);
+      int e = upper_bound_prefix(keys, a, j + 1, keys[a] >> sh1, sh1);
+      own = e - 1;
+      if (own == j) lev = d;
+    } else {
+      own = lower_bound_prefix(keys, lo, j, kj, 0);
+      if (j == lo || delta[j - 1] != kKeyLevels) lev = kKeyLevels;
+    }
+  }
+  owner[j] = own;
+  level[j] = (int8_t)lev;
+}
+
+// Range, parent and octant of every owned cell; octant masks of the parents.
+__global__ void k_cells(const uint64_t *__restrict__ keys, const int8_t *__restrict__ delta,
+                        const int32_t *__restrict__ owner, const int8_t *__restrict__ level, int64_t n,
+                        const SysInfo *__restrict__ sys, int nsys, int32_t *__restrict__ cfirst,
+                        int32_t *__restrict__ ccount, int32_t *__restrict__ cparent, int8_t *__restrict__ cdigit,
+                        int32_t *__restrict__ mask, DevInfo *info) {
+  int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (jj >= n) return;
+  const int j = (int)jj;
+  const int l = level[j];
+  if (l < 0) return;
+  const int s = system_of(sys, nsys, j);
+  const int lo = sys[s].first, hi = lo + sys[s].count;
+  const uint64_t kj = keys[j];
+  int a, b;
+  if (l < kKeyLevels) {
+    const int sh = prefix_shift(l);
+    a = lower_bound_prefix(keys, lo, j, kj >> sh, sh);
+    b = upper_bound_prefix(keys, j, hi, kj >> sh, sh) - 1;
+  } else {
+    a = j;
+    b = upper_bound_prefix(keys, j, hi, kj, 0) - 1;
+  }
+  cfirst[j] = a;
+  ccount[j] = b - a + 1;
+  const int dl = (a > lo) ? delta[a - 1] : -1;
+  const int dr = delta[b];
+  const int lp = max(dl, dr);
+  if (lp < 0) {
+    cparent[j] = -1 - s;
+    cdigit[j] = 0;
+  } else {
+    const int sp = (dl == lp) ? a - 1 : b;
+    const int P = owner[sp];
+    const int dg = key_digit(keys[a], lp + 1);
+    cparent[j] = P;
+    cdigit[j] = (int8_t)dg;
+    atomicOr(&mask[P], 1 << dg);
+  }
+  atomicMax(&info->max_level, l);
+  atomicAdd(&info->n_cells, 1);
+}
+
+// Parent of every particle: a cell (octant mask updated), a bucket, or none
+// (a system holding one particle).
+__global__ void k_particle_parents(const uint64_t *__restrict__ keys, const int8_t *__restrict__ delta,
+                                   const int32_t *__restrict__ owner, int64_t n, const SysInfo *__restrict__ sys,
+                                   int nsys, int32_t *__restrict__ pparent, int8_t *__restrict__ pdigit,
+                                   int32_t *__restrict__ mask) {
+  int64_t ii = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ii >= n) return;
+  const int i = (int)ii;
+  const int s = system_of(sys, nsys, i);
+  const int lo = sys[s].first;
+  const int dl = (i > lo) ? delta[i - 1] : -1;
+  const int dr = delta[i];
+  const int lp = max(dl, dr);
+  if (lp < 0) {
+    pparent[i] = -1 - s;
+    pdigit[i] = 0;
+    return;
+  }
+  const int sp = (dl == lp) ? i - 1 : i;
+  const int P = owner[sp];
+  pparent[i] = P;
+  if (lp == kKeyLevels) {
+    pdigit[i] = 0;  // bucket member: slot order is Morton order
+  } else {
+    const int dg = key_digit(keys[i], lp + 1);
+    pdigit[i] = (int8_t)dg;
+    atomicOr(&mask[P], 1 << dg);
+  }
+}
+
+__global__ void k_nchild(const int8_t *__restrict__ level, const int32_t *__restrict__ mask,
+                         const int32_t *__restrict__ ccount, int64_t n, int32_t *__restrict__ nchild) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int l = level[j];
+  int c = 0;
+  if (l >= 0) c = (l == kKeyLevels) ? ccount[j] : __popc(mask[j]);
+  nchild[j] = c;
+}
+
+__device__ __forceinline__ int child_slot(int P, int dg, bool bucket_member, int i, const int32_t *__restrict__ cfc,
+                                          const int32_t *__restrict__ mask, int nsys) {
+  if (bucket_member) return nsys + cfc[P] + (i - P);
+  return nsys + cfc[P] + __popc(mask[P] & ((1 << dg) - 1));
+}
+
+// Slots of the cells; particle leaf records and their raw sums.
+__global__ void k_slots(const int8_t *__restrict__ level, const int32_t *__restrict__ cparent,
+                        const int8_t *__restrict__ cdigit, const int32_t *__restrict__ pparent,
+                        const int8_t *__restrict__ pdigit, const int32_t *__restrict__ cfc,
+                        const int32_t *__restrict__ mask, const double *__restrict__ spos,
+                        const double *__restrict__ smass, int64_t n, int nsys, int64_t cap,
+                        int32_t *__restrict__ cslot, NodeRec *__restrict__ nodes, double *__restrict__ msum,
+                        int8_t *__restrict__ meta, DevInfo *info) {
+  int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (jj >= n) return;
+  const int j = (int)jj;
+  if (level[j] >= 0) {
+    const int P = cparent[j];
+    int cs = (P < 0) ? (-1 - P) : child_slot(P, cdigit[j], false, j, cfc, mask, nsys);
+    if (cs < 0 || cs >= cap) {
+      atomicOr(&info->err, kErrBuild);
+      cs = 0;
+    }
+    cslot[j] = cs;
+  }
+  // particle j
+  const int P = pparent[j];
+  int slot;
+  if (P < 0) slot = -1 - P;
+  else slot = child_slot(P, pdigit[j], level[P] == kKeyLevels, j, cfc, mask, nsys);
+  if (slot < 0 || slot >= cap) {
+    atomicOr(&info->err, kErrBuild);
+    return;
+  }
+  const double m = smass[j];
+  NodeRec r;
+  r.com[0] = spos[3 * (int64_t)j];
+  r.com[1] = spos[3 * (int64_t)j + 1];
+  r.com[2] = spos[3 * (int64_t)j + 2];
+  r.m = m;
+  r.l = 0.0;
+  r.s = 0.0;
+  r.child = -1;
+  r.nchild = 0;
+  r.first = j;
+  r.count = 1;
+  nodes[slot] = r;
+  meta[slot] = (int8_t)(32 * kParticle + 31);
+  msum[4 * (int64_t)slot] = m;
+  msum[4 * (int64_t)slot + 1] = __dmul_rn(m, r.com[0]);
+  msum[4 * (int64_t)slot + 2] = __dmul_rn(m, r.com[1]);
+  msum[4 * (int64_t)slot + 3] = __dmul_rn(m, r.com[2]);
+}
+
+__global__ void k_empty_roots(const SysInfo *__restrict__ sys, int nsys, NodeRec *__restrict__ nodes,
+                              double *__restrict__ msum, int8_t *__restrict__ meta) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nsys || sys[s].count != 0) return;
+  NodeRec r;
+  r.com[0] = r.com[1] = r.com[2] = 0.0;
+  r.m = 0.0;
+  r.l = 0.0;
+  r.s = 0.0;
+  r.child = -1;
+  r.nchild = 0;
+  r.first = sys[s].first;
+  r.count = 0;
+  nodes[s] = r;
+  meta[s] = (int8_t)(32 * kEmpty + 31);
+  for (int k = 0; k < 4; ++k) msum[4 * (int64_t)s + k] = 0.0;
+}
+
+// Moments of the cells of one level from their children's raw sums.
+__global__ void k_moments(int lev, const int8_t *__restrict__ level, const int32_t *__restrict__ cparent,
+                          const int32_t *__restrict__ cslot,
+                          const int32_t *__restrict__ cfc, const int32_t *__restrict__ nchild,
+                          const int32_t *__restrict__ cfirst, const int32_t *__restrict__ ccount,
+                          const uint64_t *__restrict__ keys, const SysInfo *__restrict__ sys, int nsys, int64_t n,
+                          int64_t cap, NodeRec *__restrict__ nodes, double *__restrict__ msum,
+                          int8_t *__restrict__ meta, DevInfo *info) {
+  int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (jj >= n) return;
+  const int j = (int)jj;
+  if (level[j] != lev) return;
+  const int c0 = nsys + cfc[j], nc = nchild[j];
+  if (c0 < 0 || nc < 0 || (int64_t)c0 + nc > cap || cslot[j] < 0 || cslot[j] >= cap) {
+    atomicOr(&info->err, kErrBuild);
+    return;
+  }
+  double m = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
+  for (int k = 0; k < nc; ++k) {
+    const double *q = msum + 4 * (int64_t)(c0 + k);
+    m = __dadd_rn(m, q[0]);
+    mx = __dadd_rn(mx, q[1]);
+    my = __dadd_rn(my, q[2]);
+    mz = __dadd_rn(mz, q[3]);
+  }
+  const int slot = cslot[j];
+  msum[4 * (int64_t)slot] = m;
+  msum[4 * (int64_t)slot + 1] = mx;
+  msum[4 * (int64_t)slot + 2] = my;
+  msum[4 * (int64_t)slot + 3] = mz;
+  const SysInfo &S = sys[system_of(sys, nsys, j)];
+  // A bucket (level 21) is opened unless a chain of single-child cells sits
+  // above it: the opening bound shrinks down a chain (theta < 2/sqrt(3)), so
+  // the chain is accepted iff its deepest cell, at level 20, is; the bucket
+  // then carries that cell's side and s.
+  int geo = lev;
+  bool always_open = false;
+  if (lev == kKeyLevels) {
+    const int P = cparent[j];
+    const int lp = (P < 0) ? -1 : (int)level[P];
+    if (lp < kKeyLevels - 1) geo = kKeyLevels - 1;
+    else always_open = true;
+  }
+  const double l = ldexp(S.side, -geo);
+  uint32_t q[3];
+  key_cells(keys[cfirst[j]], q);
+  double c[3], com[3];
+  const double mv[3] = {mx, my, mz};
+  for (int k = 0; k < 3; ++k) {
+    double h = (double)(q[k] >> (kKeyLevels - geo)) + 0.5;
+    h = __dmul_rn(h, l);
+    c[k] = __dadd_rn(S.lo[k], h);
+    com[k] = (m > 0.0) ? mv[k] / m : c[k];
+  }
+  const double dx = __dsub_rn(c[0], com[0]), dy = __dsub_rn(c[1], com[1]), dz = __dsub_rn(c[2], com[2]);
+  const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+  NodeRec r;
+  r.com[0] = com[0];
+  r.com[1] = com[1];
+  r.com[2] = com[2];
+  r.m = m;
+  r.l = always_open ? INFINITY : l;
+  r.s = sqrt(d2);
+  r.child = c0;
+  r.nchild = nc;
+  r.first = cfirst[j];
+  r.count = ccount[j];
+  nodes[slot] = r;
+  meta[slot] = (int8_t)(lev == kKeyLevels ? 32 * kBucket + lev : lev);
+}
+
+inline unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host-side driver of the build
+// ---------------------------------------------------------------------------
+
+
+
+int bbox_blocks_per_system(int nsys) {
+  int bps = 1024 / (nsys > 0 ? nsys : 1);
+  return bps < 4 ? 4 : bps;
+}
+
+void build_tree_device(TreeBuffers &B, hipStream_t s) {
+  const int64_t n = B.n;
+  const int nsys = B.nsys;
+  const int bps = bbox_blocks_per_system(nsys);
+  k_bbox_partial<<<(unsigned)(nsys * bps), 256, 0, s>>>(B.pos, B.sys, bps, B.bbox_part, B.info);
+  k_bbox_final<<<(unsigned)nsys, 64, 0, s>>>(B.bbox_part, bps, B.sys);
+  if (n == 0) {
+    B.sorted_keys = B.keys[0];
+    k_empty_roots<<<blocks_for(nsys), 256, 0, s>>>(B.sys, nsys, B.nodes, B.msum, B.meta);
+    return;
+  }
+  if (nsys > 1) k_system_of_input<<<blocks_for(n), 256, 0, s>>>(B.sys, nsys, n, B.sys_in);
+  k_keys<<<blocks_for(n), 256, 0, s>>>(B.pos, B.mass, n, nsys > 1 ? B.sys_in : nullptr, B.sys, B.keys[0],
+                                        B.vals[0], B.info);
+  int cur = radix_sort_pairs(B.keys[0], B.keys[1], B.vals[0], B.vals[1], n, 0, 64, B.hist, B.scan_tmp, s);
+  if (nsys > 1) {
+    for (int shift = 0; (nsys - 1) >> shift; shift += 8)
+      cur = radix_pass_by_system(B.keys[0], B.keys[1], B.vals[0], B.vals[1], cur, n, B.sys_in, shift, B.hist,
+                                 B.scan_tmp, s);
+  }
+  const uint64_t *keys = B.keys[cur];
+  B.sorted_keys = B.keys[cur];
+  k_gather<<<blocks_for(n), 256, 0, s>>>(B.vals[cur], B.pos, B.mass, n, B.spos, B.smass, B.perm);
+  k_delta<<<blocks_for(n), 256, 0, s>>>(keys, B.perm, nsys > 1 ? B.sys_in : nullptr, n, B.delta);
+  k_owner<<<blocks_for(n), 256, 0, s>>>(keys, B.delta, n, B.sys, nsys, B.owner, B.level);
+  fill_i32(B.mask, 0, n, s);
+  k_cells<<<blocks_for(n), 256, 0, s>>>(keys, B.delta, B.owner, B.level, n, B.sys, nsys, B.cfirst, B.ccount,
+                                         B.cparent, B.cdigit, B.mask, B.info);
+  k_particle_parents<<<blocks_for(n), 256, 0, s>>>(keys, B.delta, B.owner, n, B.sys, nsys, B.pparent, B.pdigit,
+                                                    B.mask);
+  k_nchild<<<blocks_for(n), 256, 0, s>>>(B.level, B.mask, B.ccount, n, B.nchild);
+  scan_exclusive_i32(B.nchild, B.cfc, n, &B.info->n_slots, B.scan_tmp, s);
+  k_slots<<<blocks_for(n), 256, 0, s>>>(B.level, B.cparent, B.cdigit, B.pparent, B.pdigit, B.cfc, B.mask, B.spos,
+                                         B.smass, n, nsys, B.slot_cap, B.cslot, B.nodes, B.msum, B.meta, B.info);
+  k_empty_roots<<<blocks_for(nsys), 256, 0, s>>>(B.sys, nsys, B.nodes, B.msum, B.meta);
+  for (int lev = kKeyLevels; lev >= 0; --lev)
+    k_moments<<<blocks_for(n), 256, 0, s>>>(lev, B.level, B.cparent, B.cslot, B.cfc, B.nchild, B.cfirst, B.ccount,
+                                             keys, B.sys, nsys, n, B.slot_cap, B.nodes, B.msum, B.meta, B.info);
+}
+
+}  // namespace bh

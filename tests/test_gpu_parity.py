@@ -1,0 +1,212 @@
+"""GPU path (through the C ABI) against the FP64 oracle on the same seeded inputs.
+
+Integer work (keys, permutation, tree topology, groups, list lengths) must be
+bit-exact; FP64 tree moments are summed in the same order and must be
+bit-exact; FP32 forces must meet the bar in gpu_helpers.check_forces.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_0909_0541_amd import inputs
+from gpu_helpers import TOL, check_forces, gpu_nodes, gpu_run, oracle_nonchain_nodes, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _cases():
+    rng = np.random.default_rng(5)
+    dup = np.concatenate([np.tile([[0.1, 0.2, 0.3]], (300, 1)), rng.uniform(-1, 1, (700, 3))])
+    lattice = np.stack(np.meshgrid(*[np.arange(6.0)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    return {
+        "plummer_8k": (inputs.plummer(8192, 1, with_vel=False)[0], 1.0 / 256, 0.75, 64),
+        "clustered_20k": (inputs.clustered(20000, 2, n_halos=40)[0], 1e-4, 0.6, 256),
+        "cube_5k": (inputs.uniform_cube(5000, 3)[0], 0.01, 0.5, 32),
+        "duplicates_1k": (dup, 0.01, 0.7, 16),
+        "lattice_216": (lattice, 0.05, 0.9, 8),
+        "tiny_3": (np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 2.0, 0.5]]), 0.1, 0.5, 1),
+        "ragged_4097": (inputs.plummer(4097, 9, with_vel=False)[0], 0.01, 1.0, 100),
+    }
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_sorted_keys_and_permutation_bit_exact(gpu, name):
+    pos, eps, theta, n_crit = CASES[name]
+    mass = np.full(pos.shape[0], 1.0 / pos.shape[0])
+    t = oracle.Tree(pos, mass)
+    keys_o, perm_o = t.sorted()
+    c = gpu.Context()
+    c.build_tree(to_dev(pos), to_dev(mass))
+    keys, perm = c.export_sorted()
+    assert np.array_equal(keys.cpu().numpy().view(np.uint64), keys_o)
+    assert np.array_equal(perm.cpu().numpy().astype(np.int64), perm_o)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_tree_matches_oracle(gpu, name):
+    pos, eps, theta, n_crit = CASES[name]
+    rng = np.random.default_rng(1)
+    mass = rng.uniform(0.5, 1.5, pos.shape[0]) / pos.shape[0]
+    t = oracle.Tree(pos, mass)
+    expect = oracle_nonchain_nodes(t)
+    c = gpu.Context()
+    c.build_tree(to_dev(pos), to_dev(mass))
+    got, ints, reals = gpu_nodes(c)
+    assert set(got) == set(expect)
+    bad = [k for k in got if got[k] != expect[k]]
+    assert not bad, f"{len(bad)} nodes differ, e.g. {bad[0]}: gpu {got[bad[0]]} oracle {expect[bad[0]]}"
+    st = c.get_stats()
+    assert st.n_cells == sum(1 for v in expect.values() if v[0] != 1)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_groups_and_lists_match_oracle(gpu, name):
+    pos, eps, theta, n_crit = CASES[name]
+    mass = np.full(pos.shape[0], 1.0 / pos.shape[0])
+    t = oracle.Tree(pos, mass)
+    G = t.groups(n_crit)
+    f_o, c_o, lo_o, hi_o = t.group_info()
+    ref = t.forces(eps, theta, lists_only=True)
+    c, acc, pot, st, G_g = gpu_run(gpu, pos, mass, eps, theta, n_crit)
+    assert G_g == G
+    ints, box, ll, lm = c.export_groups(lists=True)
+    ints = ints.cpu().numpy()
+    box = box.cpu().numpy()
+    assert np.array_equal(ints[:, 0], f_o) and np.array_equal(ints[:, 1], c_o)
+    assert np.array_equal(box[:, :3], lo_o) and np.array_equal(box[:, 3:], hi_o)
+    assert np.array_equal(ll.cpu().numpy(), ref["list_len"])
+    np.testing.assert_allclose(lm.cpu().numpy(), ref["list_mass"], rtol=1e-13)
+    assert st.interactions == ref["interactions"]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_forces_match_oracle(gpu, name):
+    pos, eps, theta, n_crit = CASES[name]
+    mass = np.full(pos.shape[0], 1.0 / pos.shape[0])
+    t = oracle.Tree(pos, mass)
+    t.groups(n_crit)
+    ref = t.forces(eps, theta)
+    _, acc, pot, st, _ = gpu_run(gpu, pos, mass, eps, theta, n_crit)
+    info = check_forces(acc, pot, ref)
+    print(name, info)
+
+
+def test_theta_zero_is_direct_summation(gpu):
+    pos, mass, _ = inputs.plummer(3000, 4, with_vel=False)
+    eps = 0.01
+    _, acc, pot, st, _ = gpu_run(gpu, pos, mass, eps, 0.0, 64)
+    a_d, p_d = oracle.direct(pos, mass, eps)
+    t = oracle.Tree(pos, mass)
+    t.groups(64)
+    ref = t.forces(eps, 0.0)
+    check_forces(acc, pot, ref)
+    assert st.max_list == 3000 and st.interactions == 3000 * 2999
+    np.testing.assert_allclose(ref["acc"], a_d, rtol=0, atol=1e-12 * np.abs(a_d).max())
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 63, 64, 65])
+def test_small_and_empty_inputs(gpu, n):
+    pos = np.random.default_rng(n).normal(size=(n, 3))
+    mass = np.full(n, 1.0)
+    c = gpu.Context()
+    c.build_tree(to_dev(pos.reshape(n, 3)), to_dev(mass))
+    G = c.make_groups(8)
+    acc, pot = c.compute_forces(0.05, 0.6)
+    if n == 0:
+        assert G == 0
+        return
+    t = oracle.Tree(pos, mass)
+    assert t.groups(8) == G
+    ref = t.forces(0.05, 0.6)
+    check_forces(acc.cpu().numpy().astype(np.float64), pot.cpu().numpy().astype(np.float64), ref)
+
+
+def test_all_particles_coincident(gpu):
+    pos = np.tile([[0.5, -0.25, 3.0]], (600, 1))
+    mass = np.full(600, 1.0 / 600)
+    _, acc, pot, st, G = gpu_run(gpu, pos, mass, 0.01, 0.5, 64)
+    assert G == 10
+    assert np.all(acc == 0.0)
+    np.testing.assert_allclose(pot, -(599.0 / 600) / 0.01, rtol=TOL)
+
+
+@pytest.mark.parametrize("n_crit", [1, 2, 17, 128, 256])
+def test_group_sizes_and_lane_layouts(gpu, n_crit):
+    pos, mass, _ = inputs.clustered(12000, 7, n_halos=25)
+    eps, theta = 1e-3, 0.7
+    t = oracle.Tree(pos, mass)
+    t.groups(n_crit)
+    ref = t.forces(eps, theta)
+    _, acc, pot, st, _ = gpu_run(gpu, pos, mass, eps, theta, n_crit)
+    check_forces(acc, pot, ref)
+    assert st.interactions == ref["interactions"]
+
+
+def test_per_group_theta(gpu):
+    pos, mass, _ = inputs.clustered(15000, 8, n_halos=30)
+    eps = 1e-3
+    t = oracle.Tree(pos, mass)
+    G = t.groups(64)
+    tg = np.random.default_rng(0).uniform(0.3, 1.0, G).astype(np.float32)
+    ref = t.forces(eps, 0.5, theta_g=tg.astype(np.float64))
+    _, acc, pot, st, _ = gpu_run(gpu, pos, mass, eps, 0.5, 64, theta_group=tg)
+    check_forces(acc, pot, ref)
+    assert st.interactions == ref["interactions"]
+
+
+def test_deterministic(gpu):
+    pos, mass, _ = inputs.clustered(30000, 11, n_halos=50)
+    c = gpu.Context()
+    out = []
+    for _ in range(2):
+        c.build_tree(to_dev(pos), to_dev(mass))
+        c.make_groups(128)
+        a, p = c.compute_forces(1e-4, 0.6)
+        out.append((a.cpu().numpy().copy(), p.cpu().numpy().copy()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_direct_judge_matches_oracle(gpu):
+    pos, mass, _ = inputs.clustered(20000, 12, n_halos=30)
+    idx = np.random.default_rng(3).choice(20000, 700, replace=False)
+    c = gpu.Context()
+    a, p = c.direct_sampled(to_dev(pos), to_dev(mass), 1e-4, to_dev(idx, torch.int64))
+    a_o, p_o = oracle.direct(pos, mass, 1e-4, idx)
+    np.testing.assert_allclose(a.cpu().numpy(), a_o, rtol=1e-10, atol=1e-12 * np.abs(a_o).max())
+    np.testing.assert_allclose(p.cpu().numpy(), p_o, rtol=1e-12)
+
+
+def test_argument_and_state_errors(gpu):
+    c = gpu.Context()
+    with pytest.raises(gpu.BHError) as e:
+        c.make_groups(8)
+    assert e.value.status == -4
+    pos, mass, _ = inputs.plummer(100, 1, with_vel=False)
+    c.build_tree(to_dev(pos), to_dev(mass))
+    with pytest.raises(gpu.BHError):
+        c.make_groups(0)
+    with pytest.raises(gpu.BHError):
+        c.make_groups(257)
+    c.make_groups(16)
+    with pytest.raises(gpu.BHError):
+        c.compute_forces(0.0, 0.5)
+    with pytest.raises(gpu.BHError):
+        c.compute_forces(0.01, 1.5)
+    bad = pos.copy()
+    bad[17, 1] = np.nan
+    c.build_tree(to_dev(bad), to_dev(mass))
+    with pytest.raises(gpu.BHError) as e:
+        c.make_groups(16)
+    assert e.value.status == -1
+    neg = mass.copy()
+    neg[3] = -1.0
+    c.build_tree(to_dev(pos), to_dev(neg))
+    with pytest.raises(gpu.BHError):
+        c.make_groups(16)
+    # a good build afterwards works again
+    c.build_tree(to_dev(pos), to_dev(mass))
+    assert c.make_groups(16) > 0
