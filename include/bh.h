@@ -78,15 +78,16 @@ typedef struct {
    * of the calls made since the previous bh_get_stats, and their number. */
   double t_build_ms;     /* bh_build_tree / bh_build_batch kernels */
   double t_groups_ms;    /* bh_make_groups kernels */
-  double t_force_ms;     /* the fused walk + force kernel of the force calls */
+  double t_walk_ms;      /* group walk kernel of the force calls (lists) */
+  double t_force_ms;     /* force-sum kernel of the force calls */
   int32_t n_build_calls;
   int32_t n_groups_calls;
+  int32_t n_walk_calls;
   int32_t n_force_calls;
-  int32_t pad;
 } bh_stats;
 
 typedef struct {
-  int32_t waves_per_cu;  /* persistent walk grid = CUs x waves_per_cu (default 12) */
+  int32_t waves_per_cu;  /* persistent grids = CUs x waves_per_cu; 0 (default): as many as fit */
   int32_t timing;        /* 1: record HIP events around each stage (default 0) */
 } bh_options;
 
@@ -156,9 +157,13 @@ bh_status bh_make_groups(bh_ctx *ctx, int32_t n_crit, int64_t *n_groups_out);
  *   theta_group device FP32 [n_groups], nullable: per-group theta overriding
  *   theta (values in [0, 1]; out-of-range values raise an error flag).
  *   acc device FP32 [n][3], pot device FP32 [n]: input order.
- * The list of each group is built in FP64 (MAC) and staged in on-chip memory
- * as FP32 (x - c_g, m) with c_g the group's box centre; members sum Eq. (1)
- * in FP32 with group-relative coordinates, folding partial sums into FP64. */
+ * Two kernels (the interaction-list method of Sec. 3.2): every group walks
+ * the tree once with the FP64 opening test and writes its list to HBM as FP32
+ * (x - c_g, m), c_g the group's box centre (entries close to the box also
+ * keep the FP32 rounding residue); then members sum Eq. (1) over the list in
+ * FP32, folding partial sums into FP64.  The call synchronises once, after
+ * the walk, to check that the list pool held every list (the pool grows and
+ * the walk is repeated when it did not). */
 bh_status bh_compute_forces(bh_ctx *ctx, double eps, double theta, const float *theta_group, float *acc,
                             float *pot);
 

@@ -36,8 +36,8 @@ class _Stats(C.Structure):
                 ("n_slots", C.c_int64), ("n_groups", C.c_int64), ("interactions", C.c_int64),
                 ("list_entries", C.c_int64), ("max_list", C.c_int64), ("max_level", C.c_int32),
                 ("error_flags", C.c_int32), ("t_build_ms", C.c_double), ("t_groups_ms", C.c_double),
-                ("t_force_ms", C.c_double), ("n_build_calls", C.c_int32), ("n_groups_calls", C.c_int32),
-                ("n_force_calls", C.c_int32), ("pad", C.c_int32)]
+                ("t_walk_ms", C.c_double), ("t_force_ms", C.c_double), ("n_build_calls", C.c_int32),
+                ("n_groups_calls", C.c_int32), ("n_walk_calls", C.c_int32), ("n_force_calls", C.c_int32)]
 
 
 class _Options(C.Structure):
@@ -114,11 +114,12 @@ class Stats:
     error_flags: int
     t_build_ms: float
     t_groups_ms: float
+    t_walk_ms: float
     t_force_ms: float
     n_build_calls: int
     n_groups_calls: int
+    n_walk_calls: int
     n_force_calls: int
-    pad: int
 
 
 class Context:

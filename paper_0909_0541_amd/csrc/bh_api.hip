@@ -238,6 +238,7 @@ static bh_status check_device_errors(bh_ctx *c) {
   if (e & kErrTheta) return fail(c, BH_EINVAL, "per-group theta outside [0, 1]");
   if (e & kErrBuild) return fail(c, BH_EINTERNAL, "tree build produced an inconsistent node layout");
   if (e & kErrStack) return fail(c, BH_EINTERNAL, "walk stack capacity exceeded or node range corrupt");
+  if (e & kErrPool) return fail(c, BH_EINTERNAL, "interaction list pool exhausted");
   return BH_OK;
 }
 
@@ -341,12 +342,14 @@ void bh_destroy(bh_ctx *c) {
                     &c->perm, &c->delta, &c->level, &c->cdigit, &c->pdigit, &c->owner, &c->cfirst, &c->ccount,
                     &c->cparent, &c->pparent, &c->mask, &c->nchild, &c->cfirst_child, &c->cslot, &c->scan_tmp,
                     &c->hist, &c->nodes, &c->msum, &c->meta, &c->gflag, &c->gidx, &c->glen, &c->ginfo, &c->gbox, &c->glist,
-                    &c->gmass, &c->bbox_part, &c->sys, &c->par, &c->info, &c->direct_part, &c->energy_part};
+                    &c->gmass, &c->bbox_part, &c->sys, &c->par, &c->info, &c->direct_part, &c->energy_part,
+                    &c->glists, &c->far_pool, &c->near_pool, &c->far_next, &c->near_next,
+                    &c->items, &c->item_n, &c->item_off};
   for (DevBuf *b : bufs) free_buf(*b);
   if (c->info_host) (void)hipHostFree(c->info_host);
   if (c->stage) (void)hipHostFree(c->stage);
   if (c->stage_event) (void)hipEventDestroy(c->stage_event);
-  Timer *ts[] = {&c->t_build, &c->t_groups, &c->t_force};
+  Timer *ts[] = {&c->t_build, &c->t_groups, &c->t_walk, &c->t_force};
   for (Timer *t : ts)
     for (hipEvent_t e : t->ev) (void)hipEventDestroy(e);
   delete c;
@@ -368,7 +371,7 @@ bh_status bh_get_options(const bh_ctx *c, bh_options *opt) {
 
 bh_status bh_set_options(bh_ctx *c, const bh_options *opt) {
   if (!c || !opt) return BH_EINVAL;
-  if (opt->waves_per_cu < 1 || opt->waves_per_cu > 32) return fail(c, BH_EINVAL, "waves_per_cu must be in [1, 32]");
+  if (opt->waves_per_cu < 0 || opt->waves_per_cu > 32) return fail(c, BH_EINVAL, "waves_per_cu must be in [0, 32]");
   c->opt = *opt;
   return BH_OK;
 }
@@ -458,30 +461,99 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
   if (st) return st;
   st = upload(c, c->par.p, c->par_host.data(), sizeof(SysParam) * (size_t)c->nsys);
   if (st) return st;
-  reset_force_counters(P<DevInfo>(c->info), c->stream);
-  WalkLaunch L{};
-  L.nodes = P<NodeRec>(c->nodes);
-  L.ginfo = P<int32_t>(c->ginfo);
-  L.gbox = P<double>(c->gbox);
-  L.spos = P<double>(c->spos);
-  L.smass = P<double>(c->smass);
-  L.perm = P<int32_t>(c->perm);
-  L.sys = P<SysInfo>(c->sys);
-  L.par = P<SysParam>(c->par);
-  L.theta_group = theta_group;
-  L.acc = acc;
-  L.pot = pot;
-  L.glist = P<int32_t>(c->glist);
-  L.gmass = P<double>(c->gmass);
-  L.info = P<DevInfo>(c->info);
-  L.nsys = c->nsys;
-  L.grid = c->num_cu * c->opt.waves_per_cu;
+  if (c->n == 0) {
+    c->have_forces = true;
+    return BH_OK;
+  }
+  // list pools: start from an estimate, grow to what a walk reports it needed
+  if (c->far_cap == 0) {
+    c->far_cap = (int32_t)std::max<int64_t>(4096, c->n / 16);
+    c->near_cap = (int32_t)std::max<int64_t>(4096, c->n / 64);
+  }
+  WalkListArgs W{};
+  W.nodes = P<NodeRec>(c->nodes);
+  W.ginfo = P<int32_t>(c->ginfo);
+  W.gbox = P<double>(c->gbox);
+  W.par = P<SysParam>(c->par);
+  W.theta_group = theta_group;
+  W.info = P<DevInfo>(c->info);
+  W.nsys = c->nsys;
+  W.glist = P<int32_t>(c->glist);
+  W.gmass = P<double>(c->gmass);
+  if (!c->walk_bpc) {
+    c->walk_bpc = walk_lists_blocks_per_cu();
+    c->force_bpc = force_lists_blocks_per_cu();
+  }
+  const int grid = c->num_cu * (c->opt.waves_per_cu > 0 ? c->opt.waves_per_cu : c->walk_bpc);
+  const int fgrid = c->num_cu * (c->opt.waves_per_cu > 0 ? c->opt.waves_per_cu : c->force_bpc);
+  for (int attempt = 0;; ++attempt) {
+    st = ensure(c, c->far_pool, (size_t)c->far_cap * kFarChunk * sizeof(float4), "far list pool");
+    if (st) return st;
+    st = ensure(c, c->far_next, (size_t)c->far_cap * sizeof(int32_t), "far list links");
+    if (st) return st;
+    st = ensure(c, c->near_pool, (size_t)c->near_cap * 2 * kNearChunk * sizeof(float4), "near list pool");
+    if (st) return st;
+    st = ensure(c, c->near_next, (size_t)c->near_cap * sizeof(int32_t), "near list links");
+    if (st) return st;
+    st = ensure(c, c->glists, (size_t)4 * sizeof(int32_t) * (size_t)std::max<int64_t>(c->n, 1), "group lists");
+    if (st) return st;
+    W.far_pool = P<float4>(c->far_pool);
+    W.near_pool = P<float4>(c->near_pool);
+    W.far_next = P<int32_t>(c->far_next);
+    W.near_next = P<int32_t>(c->near_next);
+    W.far_cap = c->far_cap;
+    W.near_cap = c->near_cap;
+    W.glists = P<int32_t>(c->glists);
+    reset_list_counters(P<DevInfo>(c->info), c->stream);
+    st = timer_start(c, c->t_walk);
+    if (st) return st;
+    walk_lists_device(W, grid, c->stream);
+    st = timer_stop(c, c->t_walk);
+    if (st) return st;
+    st = hip_check(c, hipGetLastError(), "kernel launch (walk)");
+    if (st) return st;
+    // the pools must have held every list before the sums may run
+    st = hip_check(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(DevInfo), hipMemcpyDeviceToHost, c->stream),
+                   "hipMemcpyAsync info");
+    if (st) return st;
+    st = hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (st) return st;
+    if (!(c->info_host->err & kErrPool)) break;
+    if (attempt > 0) return fail(c, BH_EINTERNAL, "interaction list pool still too small after growing");
+    c->far_cap = std::max(c->far_cap, (int32_t)(c->info_host->far_chunks + c->info_host->far_chunks / 4 + 64));
+    c->near_cap = std::max(c->near_cap, (int32_t)(c->info_host->near_chunks + c->info_host->near_chunks / 4 + 64));
+  }
+  const size_t gcap = (size_t)std::max<int64_t>(c->n, 1);
+  st = ensure(c, c->items, 2 * sizeof(int32_t) * (gcap + gcap / 64 + 64), "force items");
+  if (st) return st;
+  st = ensure(c, c->item_n, sizeof(int32_t) * gcap, "force item counts");
+  if (st) return st;
+  st = ensure(c, c->item_off, sizeof(int32_t) * gcap, "force item offsets");
+  if (st) return st;
+  force_items_device(P<int32_t>(c->ginfo), P<DevInfo>(c->info), (int64_t)gcap, P<int32_t>(c->item_n),
+                     P<int32_t>(c->item_off), P<int32_t>(c->items), c->scan_tmp.p, c->stream);
+  ForceArgs F{};
+  F.items = P<int32_t>(c->items);
+  F.ginfo = P<int32_t>(c->ginfo);
+  F.gbox = P<double>(c->gbox);
+  F.glists = P<int32_t>(c->glists);
+  F.far_pool = P<float4>(c->far_pool);
+  F.near_pool = P<float4>(c->near_pool);
+  F.far_next = P<int32_t>(c->far_next);
+  F.near_next = P<int32_t>(c->near_next);
+  F.spos = P<double>(c->spos);
+  F.smass = P<double>(c->smass);
+  F.perm = P<int32_t>(c->perm);
+  F.par = P<SysParam>(c->par);
+  F.acc = acc;
+  F.pot = pot;
+  F.info = P<DevInfo>(c->info);
   st = timer_start(c, c->t_force);
   if (st) return st;
-  if (c->n > 0) walk_force_device(L, c->stream);
+  force_lists_device(F, fgrid, c->stream);
   st = timer_stop(c, c->t_force);
   if (st) return st;
-  st = hip_check(c, hipGetLastError(), "kernel launch (walk)");
+  st = hip_check(c, hipGetLastError(), "kernel launch (force)");
   if (st) return st;
   c->have_forces = true;
   return BH_OK;
@@ -527,6 +599,7 @@ bh_status bh_get_stats(bh_ctx *c, bh_stats *out) {
   }
   out->t_build_ms = timer_take(c->t_build, &out->n_build_calls);
   out->t_groups_ms = timer_take(c->t_groups, &out->n_groups_calls);
+  out->t_walk_ms = timer_take(c->t_walk, &out->n_walk_calls);
   out->t_force_ms = timer_take(c->t_force, &out->n_force_calls);
   return st;
 }

@@ -10,6 +10,14 @@ namespace bh {
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+// One value per wavefront from an atomic counter: every lane executes the
+// atomic (lane 0 adds one, the others zero) so that no divergent branch
+// precedes the broadcast of lane 0's result.  Call with all lanes active.
+__device__ __forceinline__ int take_one(int *counter, int lane) {
+  const int t = atomicAdd(counter, lane == 0 ? 1 : 0);
+  return __builtin_amdgcn_readfirstlane(t);
+}
+
 // Number of set bits of m below this lane.
 __device__ __forceinline__ int rank_below(unsigned long long m) {
   return (int)__popcll(m & __lanemask_lt());

@@ -59,8 +59,20 @@ struct DevInfo {
   unsigned long long interactions;
   unsigned long long list_entries;
   int32_t max_list;
-  int32_t pad;
+  int32_t queue2;         // force work queue head
+  int32_t far_chunks;     // list chunks taken (may exceed the pool: then it is the need)
+  int32_t near_chunks;
+  int32_t n_items;        // force work items (group, member block)
+  int32_t pad2;
 };
+
+// Interaction lists: chunks of kFarChunk far entries (float4 x - c_g, m) and
+// of kNearChunk near entries (kNearChunk float4 values, then kNearChunk
+// float4 rounding residues), 8 KiB each.
+constexpr int kFarChunk = 512;
+constexpr int kNearChunk = 256;
+// Near entries: within kNearFrac times the box half-diagonal of the box.
+constexpr double kNearFrac = 0.1;
 
 enum : int32_t {
   kErrNonFinitePos = 1,
@@ -68,6 +80,7 @@ enum : int32_t {
   kErrStack = 4,
   kErrTheta = 8,
   kErrBuild = 16,
+  kErrPool = 32,
 };
 
 // Growable device buffer.
@@ -90,7 +103,8 @@ struct bh_ctx {
   int device = 0;
   int num_cu = 0;
   std::string err;
-  bh_options opt{12, 0};
+  bh_options opt{0, 0};
+  int walk_bpc = 0, force_bpc = 0;  // resident blocks per CU of the persistent kernels
 
   // current tree
   int64_t n = 0;
@@ -129,6 +143,11 @@ struct bh_ctx {
   bh::DevBuf ginfo;             // int32 [G][3] first, count, system
   bh::DevBuf gbox;              // FP64 [G][6]
   bh::DevBuf glist;             // int32 [G] list length of the last force call
+  bh::DevBuf glists;            // int32 [G][4] far head, far count, near head, near count
+  bh::DevBuf items, item_n, item_off;  // force work items and their per-group counts / offsets
+  bh::DevBuf far_pool, near_pool;  // list chunks
+  bh::DevBuf far_next, near_next;  // int32 chunk links
+  int32_t far_cap = 0, near_cap = 0;  // pool capacities in chunks
   bh::DevBuf gmass;             // FP64 [G] list mass of the last force call
   bh::DevBuf bbox_part;         // FP64 bbox partials
   bh::DevBuf sys;               // SysInfo [nsys]
@@ -145,7 +164,7 @@ struct bh_ctx {
   bool stage_event_used = false;
   uint64_t *sorted_keys = nullptr;    // the key buffer holding the sorted keys
 
-  bh::Timer t_build, t_groups, t_force;
+  bh::Timer t_build, t_groups, t_walk, t_force;
 };
 
 namespace bh {
@@ -219,26 +238,50 @@ struct GroupBuffers {
 void make_groups_device(GroupBuffers &B, hipStream_t s);
 void reset_force_counters(DevInfo *info, hipStream_t s);
 
-// k_walk.hip
-struct WalkLaunch {
+// k_walk.hip: group walk writing the interaction lists
+struct WalkListArgs {
   const NodeRec *nodes;
   const int32_t *ginfo;
   const double *gbox;
+  const SysParam *par;
+  const float *theta_group;
+  DevInfo *info;
+  int nsys;
+  float4 *far_pool;
+  float4 *near_pool;
+  int32_t *far_next;
+  int32_t *near_next;
+  int far_cap, near_cap;
+  int32_t *glists;
+  int32_t *glist;
+  double *gmass;
+};
+void walk_lists_device(const WalkListArgs &a, int grid, hipStream_t s);
+int walk_lists_blocks_per_cu();  // resident single-wave blocks per CU
+
+// k_force.hip: force sums over the lists
+struct ForceArgs {
+  const int32_t *ginfo;
+  const double *gbox;
+  const int32_t *glists;
+  const float4 *far_pool;
+  const float4 *near_pool;
+  const int32_t *far_next;
+  const int32_t *near_next;
   const double *spos;
   const double *smass;
   const int32_t *perm;
-  const SysInfo *sys;
   const SysParam *par;
-  const float *theta_group;
   float *acc;
   float *pot;
-  int32_t *glist;
-  double *gmass;
   DevInfo *info;
-  int nsys;
-  int grid;
+  const int32_t *items;  // [n_items][2] group, member block
 };
-void walk_force_device(const WalkLaunch &L, hipStream_t s);
+void force_items_device(const int32_t *ginfo, DevInfo *info, int64_t cap, int32_t *nblk, int32_t *off,
+                        int32_t *items, void *scan_tmp, hipStream_t s);
+void force_lists_device(const ForceArgs &a, int grid, hipStream_t s);
+int force_lists_blocks_per_cu();
+void reset_list_counters(DevInfo *info, hipStream_t s);
 
 // k_misc.hip
 size_t direct_part_bytes(int64_t n, int64_t s, int num_cu, int64_t *chunk, int64_t *nchunk);

@@ -1,0 +1,267 @@
+// Force sum over the interaction lists (Eq. 1, FP32 with group-relative
+// coordinates, partial sums folded into FP64).
+//
+// Work items are (group, block of at most 64 members); a persistent grid of
+// single-wave workgroups pulls items from an atomic queue.  A block of m
+// members uses R lane partitions of W = 64/R >= m lanes, one member per lane;
+// partition `part` takes list entries part, part + R, ...  With R = 1 every
+// lane reads the same entry, so entries are fetched with scalar loads and used
+// as scalar operands.  Per term a lane computes dx = x_j - x_i (near entries:
+// from the FP32 value and its rounding residue), r^2 = |dx|^2 + eps^2 (FMA),
+// v_rsq_f32, and accumulates m r^-3 dx and m r^-1, the terms of a block of
+// entries written stage by stage so that dependent instructions issue far
+// apart.  After each list chunk the FP32 partial sums are folded into FP64.  A
+// member's own entry is in the near list with dx = 0 exactly: it adds 0 force
+// and m_i/eps potential, removed at the end.
+#include "bh_device.h"
+
+namespace bh {
+
+namespace {
+
+struct Member {
+  float x, y, z;     // FP32 x_i - c_g
+  float lx, ly, lz;  // rounding residue of x_i - c_g
+  float ax, ay, az, pt;
+  double dx, dy, dz, dp;
+};
+
+// U entries (value e, rounding residue l when NEAR) against this lane's
+// member, written stage by stage across the U independent terms.
+template <int U, bool NEAR>
+__device__ __forceinline__ void terms(Member &M, const float4 (&e)[U], const float4 (&l)[U], float eps2) {
+  float dx[U], dy[U], dz[U], q[U], mr[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    dx[u] = e[u].x - M.x;
+    dy[u] = e[u].y - M.y;
+    dz[u] = e[u].z - M.z;
+  }
+  if (NEAR) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      dx[u] += l[u].x - M.lx;
+      dy[u] += l[u].y - M.ly;
+      dz[u] += l[u].z - M.lz;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) q[u] = __builtin_fmaf(dx[u], dx[u], eps2);
+#pragma unroll
+  for (int u = 0; u < U; ++u) q[u] = __builtin_fmaf(dy[u], dy[u], q[u]);
+#pragma unroll
+  for (int u = 0; u < U; ++u) q[u] = __builtin_fmaf(dz[u], dz[u], q[u]);
+#pragma unroll
+  for (int u = 0; u < U; ++u) q[u] = __builtin_amdgcn_rsqf(q[u]);  // 1/r
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    mr[u] = e[u].w * q[u];
+    q[u] = q[u] * q[u];  // 1/r^2
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) q[u] = mr[u] * q[u];  // m/r^3
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    M.ax = __builtin_fmaf(q[u], dx[u], M.ax);
+    M.ay = __builtin_fmaf(q[u], dy[u], M.ay);
+    M.az = __builtin_fmaf(q[u], dz[u], M.az);
+    M.pt += mr[u];
+  }
+}
+
+__device__ __forceinline__ void fold(Member &M) {
+  M.dx += (double)M.ax;
+  M.dy += (double)M.ay;
+  M.dz += (double)M.az;
+  M.dp += (double)M.pt;
+  M.ax = M.ay = M.az = M.pt = 0.0f;
+}
+
+constexpr int kU = 8;  // entries per block of terms
+
+// n entries of one chunk: values at h[0..n), residues at l[0..n) when NEAR.
+template <bool NEAR>
+__device__ __forceinline__ void chunk_sum(Member &M, const float4 *__restrict__ h, const float4 *__restrict__ l,
+                                          int n, int R, int part, float eps2) {
+  float4 e[kU], r[kU];
+  if (R == 1) {
+    // every lane takes the same entries: scalar loads, scalar operands; the
+    // next block is fetched while the current one is summed
+    int t = 0;
+    if (n >= kU) {
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        e[u] = h[u];
+        r[u] = NEAR ? l[u] : e[u];
+      }
+      for (t = kU; t + kU <= n; t += kU) {
+        float4 ne[kU], nr[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          ne[u] = h[t + u];
+          nr[u] = NEAR ? l[t + u] : ne[u];
+        }
+        terms<kU, NEAR>(M, e, r, eps2);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          e[u] = ne[u];
+          r[u] = nr[u];
+        }
+      }
+      terms<kU, NEAR>(M, e, r, eps2);
+    }
+    for (; t < n; ++t) {
+      const float4 e1[1] = {h[t]}, r1[1] = {NEAR ? l[t] : h[t]};
+      terms<1, NEAR>(M, e1, r1, eps2);
+    }
+  } else {
+    // partition `part` takes entries part, part + R, ...
+    const int mine = (n - part + R - 1) / R;
+    int t = 0;
+    for (; t + 4 <= mine; t += 4) {
+      float4 e4[4], r4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        e4[u] = h[(t + u) * R + part];
+        r4[u] = NEAR ? l[(t + u) * R + part] : e4[u];
+      }
+      terms<4, NEAR>(M, e4, r4, eps2);
+    }
+    for (; t < mine; ++t) {
+      const float4 e1[1] = {h[t * R + part]}, r1[1] = {NEAR ? l[t * R + part] : h[t * R + part]};
+      terms<1, NEAR>(M, e1, r1, eps2);
+    }
+  }
+  fold(M);
+}
+
+// The list data is read-only here; as separate restrict arguments the
+// compiler can fetch wave-uniform entries with scalar loads.
+__global__ __launch_bounds__(kWave) void k_force_lists(ForceArgs a, const float4 *__restrict__ far_pool,
+                                                       const int32_t *__restrict__ far_next,
+                                                       const float4 *__restrict__ near_pool,
+                                                       const int32_t *__restrict__ near_next,
+                                                       const int32_t *__restrict__ glists,
+                                                       const int32_t *__restrict__ items) {
+  const int lane = lane_id();
+  const int T = a.info->n_items;
+  for (;;) {
+    const int it = take_one(&a.info->queue2, lane);
+    if (it >= T) break;
+    const int g = items[2 * it], blk = items[2 * it + 1];
+    const int gf = a.ginfo[3 * g], gc = a.ginfo[3 * g + 1], gs = a.ginfo[3 * g + 2];
+    const int fh = glists[4 * g], fn = glists[4 * g + 1], nh = glists[4 * g + 2], nn = glists[4 * g + 3];
+    if ((fn > 0 && fh < 0) || (nn > 0 && nh < 0)) continue;  // incomplete list (reported by the walk)
+    // members [b0, b1) of the group: blocks of near-equal size, at most 64
+    const int nb = (gc + kWave - 1) / kWave;
+    const int b0 = (int)((int64_t)gc * blk / nb), b1 = (int)((int64_t)gc * (blk + 1) / nb);
+    const int m = b1 - b0;
+    int R = 1;
+    while (R < kWave && m * (2 * R) <= kWave) R *= 2;
+    const int W = kWave / R;
+    const int part = lane / W, u = lane % W;
+
+    double cen[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      cen[k] = __dmul_rn(__dadd_rn(a.gbox[6 * (int64_t)g + k], a.gbox[6 * (int64_t)g + 3 + k]), 0.5);
+    const double eps = a.par[gs].eps;
+    const float eps2 = (float)(eps * eps);
+
+    Member M;
+    {
+      double rx = 0.0, ry = 0.0, rz = 0.0;
+      if (u < m) {
+        const double *q = a.spos + 3 * (int64_t)(gf + b0 + u);
+        rx = __dsub_rn(q[0], cen[0]);
+        ry = __dsub_rn(q[1], cen[1]);
+        rz = __dsub_rn(q[2], cen[2]);
+      }
+      M.x = (float)rx;
+      M.y = (float)ry;
+      M.z = (float)rz;
+      M.lx = (float)__dsub_rn(rx, (double)M.x);
+      M.ly = (float)__dsub_rn(ry, (double)M.y);
+      M.lz = (float)__dsub_rn(rz, (double)M.z);
+      M.ax = M.ay = M.az = M.pt = 0.0f;
+      M.dx = M.dy = M.dz = M.dp = 0.0;
+    }
+
+    int ch = fh;
+    for (int left = fn; left > 0;) {
+      const int n = min(left, kFarChunk);
+      const float4 *base = far_pool + (int64_t)ch * kFarChunk;
+      chunk_sum<false>(M, base, base, n, R, part, eps2);
+      left -= n;
+      if (left > 0) ch = far_next[ch];
+    }
+    ch = nh;
+    for (int left = nn; left > 0;) {
+      const int n = min(left, kNearChunk);
+      const float4 *base = near_pool + (int64_t)ch * (2 * kNearChunk);
+      chunk_sum<true>(M, base, base + kNearChunk, n, R, part, eps2);
+      left -= n;
+      if (left > 0) ch = near_next[ch];
+    }
+
+    // reduce partitions, remove the self term, write in input order
+    double vx = M.dx, vy = M.dy, vz = M.dz, vp = M.dp;
+    for (int b = W; b < kWave; b <<= 1) {
+      vx += shfl_xor_d(vx, b);
+      vy += shfl_xor_d(vy, b);
+      vz += shfl_xor_d(vz, b);
+      vp += shfl_xor_d(vp, b);
+    }
+    if (part == 0 && u < m) {
+      const int i = gf + b0 + u;
+      const float self_ri = __builtin_amdgcn_rsqf(__builtin_fmaf(0.0f, 0.0f, eps2));
+      const double self = (double)((float)a.smass[i] * self_ri);
+      const int o = a.perm[i];
+      a.acc[3 * (int64_t)o] = (float)vx;
+      a.acc[3 * (int64_t)o + 1] = (float)vy;
+      a.acc[3 * (int64_t)o + 2] = (float)vz;
+      a.pot[o] = (float)(self - vp);
+    }
+  }
+}
+
+// Member blocks per group (ceil(count / 64)).
+__global__ void k_item_counts(const int32_t *__restrict__ ginfo, const DevInfo *__restrict__ info, int64_t cap,
+                              int32_t *__restrict__ nblk) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= cap) return;
+  nblk[g] = (g < info->n_groups) ? (ginfo[3 * g + 1] + kWave - 1) / kWave : 0;
+}
+
+__global__ void k_item_fill(const int32_t *__restrict__ nblk, const int32_t *__restrict__ off,
+                            const DevInfo *__restrict__ info, int32_t *__restrict__ items) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= info->n_groups) return;
+  for (int b = 0; b < nblk[g]; ++b) {
+    items[2 * ((int64_t)off[g] + b)] = (int32_t)g;
+    items[2 * ((int64_t)off[g] + b) + 1] = b;
+  }
+}
+
+}  // namespace
+
+void force_items_device(const int32_t *ginfo, DevInfo *info, int64_t cap, int32_t *nblk, int32_t *off,
+                        int32_t *items, void *scan_tmp, hipStream_t s) {
+  const unsigned blocks = (unsigned)((cap + 255) / 256);
+  k_item_counts<<<blocks, 256, 0, s>>>(ginfo, info, cap, nblk);
+  scan_exclusive_i32(nblk, off, cap, &info->n_items, scan_tmp, s);
+  k_item_fill<<<blocks, 256, 0, s>>>(nblk, off, info, items);
+}
+
+int force_lists_blocks_per_cu() {
+  int b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_force_lists, kWave, 0) != hipSuccess || b < 1) b = 8;
+  return b;
+}
+
+void force_lists_device(const ForceArgs &a, int grid, hipStream_t s) {
+  k_force_lists<<<(unsigned)grid, kWave, 0, s>>>(a, a.far_pool, a.far_next, a.near_pool, a.near_next, a.glists,
+                                                 a.items);
+}
+
+}  // namespace bh

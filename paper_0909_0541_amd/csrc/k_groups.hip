@@ -105,9 +105,13 @@ __global__ __launch_bounds__(256) void k_group_box(const int32_t *__restrict__ g
 __global__ void k_reset_force_counters(DevInfo *info) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     info->queue = 0;
+    info->queue2 = 0;
+    info->far_chunks = 0;
+    info->near_chunks = 0;
     info->interactions = 0;
     info->list_entries = 0;
     info->max_list = 0;
+    info->err &= ~kErrPool;
   }
 }
 
@@ -133,5 +137,6 @@ void make_groups_device(GroupBuffers &B, hipStream_t s) {
 }
 
 void reset_force_counters(DevInfo *info, hipStream_t s) { k_reset_force_counters<<<1, 64, 0, s>>>(info); }
+void reset_list_counters(DevInfo *info, hipStream_t s) { k_reset_force_counters<<<1, 64, 0, s>>>(info); }
 
 }  // namespace bh
