@@ -212,6 +212,8 @@ static bh_status ensure_particles(bh_ctx *c, int64_t n, int nsys) {
       {&c->nodes, sizeof(NodeRec) * slots, "nodes"},
       {&c->msum, 32 * slots, "msum"},
       {&c->meta, slots, "meta"},
+      {&c->levels, 3 * 24 * sizeof(int32_t), "level table"},
+      {&c->lcells, 4 * N, "cells by level"},
       {&c->gflag, 4 * N, "gflag"},        {&c->gidx, 4 * N, "gidx"},
       {&c->glen, 4 * N, "glen"},          {&c->ginfo, 12 * N, "ginfo"},
       {&c->gbox, 48 * N, "gbox"},         {&c->glist, 4 * N, "glist"},
@@ -298,6 +300,10 @@ static bh_status build_common(bh_ctx *c, int32_t nsys, const int64_t *offsets, c
   B.nodes = P<NodeRec>(c->nodes);
   B.msum = P<double>(c->msum);
   B.meta = P<int8_t>(c->meta);
+  B.lcount = P<int32_t>(c->levels);
+  B.loff = B.lcount + 24;
+  B.lcursor = B.lcount + 48;
+  B.lcells = P<int32_t>(c->lcells);
   B.slot_cap = (int64_t)std::min({c->nodes.bytes / sizeof(NodeRec), c->msum.bytes / 32, c->meta.bytes});
   build_tree_device(B, c->stream);
   c->sorted_keys = B.sorted_keys;
@@ -341,7 +347,7 @@ void bh_destroy(bh_ctx *c) {
   DevBuf *bufs[] = {&c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->sys_in, &c->spos, &c->smass,
                     &c->perm, &c->delta, &c->level, &c->cdigit, &c->pdigit, &c->owner, &c->cfirst, &c->ccount,
                     &c->cparent, &c->pparent, &c->mask, &c->nchild, &c->cfirst_child, &c->cslot, &c->scan_tmp,
-                    &c->hist, &c->nodes, &c->msum, &c->meta, &c->gflag, &c->gidx, &c->glen, &c->ginfo, &c->gbox, &c->glist,
+                    &c->hist, &c->nodes, &c->msum, &c->meta, &c->levels, &c->lcells, &c->gflag, &c->gidx, &c->glen, &c->ginfo, &c->gbox, &c->glist,
                     &c->gmass, &c->bbox_part, &c->sys, &c->par, &c->info, &c->direct_part, &c->energy_part,
                     &c->glists, &c->far_pool, &c->near_pool, &c->far_next, &c->near_next,
                     &c->items, &c->item_n, &c->item_off};

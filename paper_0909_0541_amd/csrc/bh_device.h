@@ -90,6 +90,40 @@ __device__ __forceinline__ int upper_bound_prefix(const uint64_t *__restrict__ k
   return lo;
 }
 
+// Galloping searches around a known position j whose key prefix equals p:
+// steps of 1, 2, 4, ... away from j, then a binary search in the last step,
+// so that small cells cost a few cached loads instead of a search over the
+// whole system.
+// First index in [lo, j] whose prefix equals p.
+__device__ __forceinline__ int gallop_first(const uint64_t *__restrict__ keys, int lo, int j, uint64_t p, int sh) {
+  int good = j, bad = lo - 1;
+  for (int step = 1;; step <<= 1) {
+    const int probe = good - step;
+    if (probe < lo) break;
+    if ((keys[probe] >> sh) < p) {
+      bad = probe;
+      break;
+    }
+    good = probe;
+  }
+  return lower_bound_prefix(keys, bad + 1, good, p, sh);
+}
+
+// First index in (j, hi) whose prefix exceeds p (hi if none).
+__device__ __forceinline__ int gallop_past(const uint64_t *__restrict__ keys, int j, int hi, uint64_t p, int sh) {
+  int good = j, bad = hi;
+  for (int step = 1;; step <<= 1) {
+    const int probe = good + step;
+    if (probe >= hi) break;
+    if ((keys[probe] >> sh) > p) {
+      bad = probe;
+      break;
+    }
+    good = probe;
+  }
+  return upper_bound_prefix(keys, good + 1, bad, p, sh);
+}
+
 // System owning Morton position j (systems occupy consecutive ranges).
 __device__ __forceinline__ int system_of(const SysInfo *__restrict__ sys, int nsys, int j) {
   int lo = 0, hi = nsys - 1;

@@ -137,6 +137,8 @@ struct bh_ctx {
   bh::DevBuf nodes;             // NodeRec [slots]
   bh::DevBuf msum;              // FP64 [slots][4] raw sums m, m x, m y, m z
   bh::DevBuf meta;              // int8 [slots] 32 * kind + level (inspection only)
+  bh::DevBuf levels;            // int32 level counts, offsets and cursors (3 x 24)
+  bh::DevBuf lcells;            // int32 cells grouped by level
   bh::DevBuf gflag;             // int32 group start flags
   bh::DevBuf gidx;              // int32 exclusive scan of the flags (group index)
   bh::DevBuf glen;              // int32 group length at its start position
@@ -213,6 +215,8 @@ struct TreeBuffers {
   NodeRec *nodes;
   double *msum;
   int8_t *meta;           // per slot: 32 * kind + level (export only)
+  int32_t *lcount, *loff, *lcursor;  // cells per level: counts, offsets [23], scatter cursors
+  int32_t *lcells;                   // cell owner positions grouped by level
   int64_t slot_cap;       // capacity of nodes/msum/meta in slots
   uint64_t *sorted_keys;  // out: the buffer holding the sorted keys
 };

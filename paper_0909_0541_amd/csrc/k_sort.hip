@@ -2,7 +2,9 @@
 //
 // Per pass: per-tile digit histograms (LDS counters), one exclusive scan of
 // the digit-major histogram table, then a scatter in which each wave ranks its
-// keys stably with ballot-based peer masks and per-wave digit counters in LDS.
+// keys stably with ballot-based peer masks and per-wave digit counters in LDS;
+// the tile is staged in LDS in digit order so that the writes to HBM are runs
+// of consecutive addresses.
 // A tile is 4 waves x 16 chunks x 64 keys = 4096 keys; keys of wave w, chunk
 // c, lane l sit at tile offset w*1024 + c*64 + l, so (w, c, l) order is input
 // order and the sort is stable.
@@ -18,22 +20,24 @@ constexpr int kSortWaves = kSortThreads / kWave;
 constexpr int kSortTile = kSortThreads * kSortChunks;
 constexpr int kRadix = 256;
 
+// Digit of a (key, value) pair: 8 bits of the key ...
 struct KeyDigit {
-  const uint64_t *keys;
   int bit;
-  __device__ __forceinline__ int operator()(int64_t i, uint32_t) const { return (int)((keys[i] >> bit) & 255u); }
+  __device__ __forceinline__ int of(uint64_t k, uint32_t) const { return (int)((k >> bit) & 255u); }
 };
 
+// ... or 8 bits of the system of the input row the value names.
 struct SysDigit {
   const int32_t *sys_in;
   int shift;
-  __device__ __forceinline__ int operator()(int64_t, uint32_t v) const {
+  __device__ __forceinline__ int of(uint64_t, uint32_t v) const {
     return (int)(((uint32_t)sys_in[v] >> shift) & 255u);
   }
 };
 
 template <class Digit>
-__global__ __launch_bounds__(kSortThreads) void k_hist(const uint32_t *__restrict__ vals, int64_t n, Digit dig,
+__global__ __launch_bounds__(kSortThreads) void k_hist(const uint64_t *__restrict__ keys,
+                                                       const uint32_t *__restrict__ vals, int64_t n, Digit dig,
                                                        int64_t ntiles, uint32_t *__restrict__ hist) {
   __shared__ uint32_t cnt[kSortWaves][kRadix];
   const int w = threadIdx.x / kWave, lane = lane_id();
@@ -43,7 +47,7 @@ __global__ __launch_bounds__(kSortThreads) void k_hist(const uint32_t *__restric
 #pragma unroll 4
   for (int c = 0; c < kSortChunks; ++c) {
     int64_t i = base + c * kWave + lane;
-    if (i < n) atomicAdd(&cnt[w][dig(i, vals[i])], 1u);
+    if (i < n) atomicAdd(&cnt[w][dig.of(keys[i], vals[i])], 1u);
   }
   __syncthreads();
   for (int d = threadIdx.x; d < kRadix; d += kSortThreads) {
@@ -59,10 +63,15 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint64_t *__rest
                                                           int64_t n, Digit dig, int64_t ntiles,
                                                           const uint32_t *__restrict__ offs) {
   __shared__ uint32_t cnt[kSortWaves][kRadix];
+  __shared__ uint32_t dstart[kRadix];  // tile-local start of each digit
+  __shared__ uint64_t skey[kSortTile];
+  __shared__ uint32_t sval[kSortTile];
   const int w = threadIdx.x / kWave, lane = lane_id();
   for (int d = threadIdx.x; d < kSortWaves * kRadix; d += kSortThreads) (&cnt[0][0])[d] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)w * (kSortChunks * kWave);
+  const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+  const int64_t base = tile0 + (int64_t)w * (kSortChunks * kWave);
+  const int tile_n = (int)min((int64_t)kSortTile, n - tile0);
   uint64_t key[kSortChunks];
   uint32_t val[kSortChunks];
   int rank[kSortChunks];
@@ -73,7 +82,7 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint64_t *__rest
     bool ok = i < n;
     key[c] = ok ? kin[i] : 0;
     val[c] = ok ? vin[i] : 0;
-    int d = ok ? dig(i, val[c]) : 0;
+    int d = ok ? dig.of(key[c], val[c]) : 0;
     digit[c] = d;
     unsigned long long valid = __ballot(ok);
     unsigned long long peers = valid;
@@ -91,24 +100,54 @@ __global__ __launch_bounds__(kSortThreads) void k_scatter(const uint64_t *__rest
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  // per-digit offset of this wave = counts of the earlier waves
-  for (int d = threadIdx.x; d < kRadix; d += kSortThreads) {
-    uint32_t run = offs[(int64_t)d * ntiles + blockIdx.x];
+  // tile-local offsets: digits in order, within a digit the waves in order
+  if (threadIdx.x < kRadix) {
+    const int d = threadIdx.x;
+    uint32_t tot = 0;
     for (int k = 0; k < kSortWaves; ++k) {
       uint32_t c = cnt[k][d];
-      cnt[k][d] = run;
-      run += c;
+      cnt[k][d] = tot;
+      tot += c;
+    }
+    dstart[d] = tot;  // digit total for now, turned into a start below
+  }
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    // exclusive scan of the 256 digit totals by one wave (4 per lane)
+    uint32_t v[4], s = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[q] = dstart[4 * threadIdx.x + q];
+      s += v[q];
+    }
+    const uint32_t inc = (uint32_t)wave_inclusive_sum((int)s);
+    uint32_t run = inc - s;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      dstart[4 * threadIdx.x + q] = run;
+      run += v[q];
     }
   }
   __syncthreads();
+  // stage the tile in LDS in digit order
 #pragma unroll
   for (int c = 0; c < kSortChunks; ++c) {
-    int64_t i = base + c * kWave + lane;
+    const int64_t i = base + c * kWave + lane;
     if (i < n) {
-      uint32_t dst = cnt[w][digit[c]] + (uint32_t)rank[c];
-      kout[dst] = key[c];
-      vout[dst] = val[c];
+      const uint32_t p = dstart[digit[c]] + cnt[w][digit[c]] + (uint32_t)rank[c];
+      skey[p] = key[c];
+      sval[p] = val[c];
     }
+  }
+  __syncthreads();
+  // write out: consecutive threads hold consecutive positions of one digit run
+  for (int p = threadIdx.x; p < tile_n; p += kSortThreads) {
+    const uint64_t k = skey[p];
+    const uint32_t v = sval[p];
+    const int d = dig.of(k, v);
+    const uint32_t dst = offs[(int64_t)d * ntiles + blockIdx.x] + (uint32_t)p - dstart[d];
+    kout[dst] = k;
+    vout[dst] = v;
   }
 }
 
@@ -121,7 +160,7 @@ template <class Digit>
 void one_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout, uint32_t *vout, int64_t n, Digit dig,
               uint32_t *hist, void *scan_tmp, hipStream_t s) {
   int64_t ntiles = (n + kSortTile - 1) / kSortTile;
-  k_hist<Digit><<<(unsigned)ntiles, kSortThreads, 0, s>>>(vin, n, dig, ntiles, hist);
+  k_hist<Digit><<<(unsigned)ntiles, kSortThreads, 0, s>>>(kin, vin, n, dig, ntiles, hist);
   scan_exclusive_i32((const int32_t *)hist, (int32_t *)hist, ntiles * kRadix, nullptr, scan_tmp, s);
   k_scatter<Digit><<<(unsigned)ntiles, kSortThreads, 0, s>>>(kin, vin, kout, vout, n, dig, ntiles, hist);
 }
@@ -145,8 +184,7 @@ int radix_sort_pairs(uint64_t *k0, uint64_t *k1, uint32_t *v0, uint32_t *v1, int
   int cur = 0;
   if (n <= 1) return cur;
   for (int bit = bit0; bit < bit1; bit += 8) {
-    KeyDigit dig{k[cur], bit};
-    // the digit functor reads the key by index from the input buffer
+    KeyDigit dig{bit};
     one_pass(k[cur], v[cur], k[cur ^ 1], v[cur ^ 1], n, dig, hist, scan_tmp, s);
     cur ^= 1;
   }

@@ -16,6 +16,8 @@
 // summed level by level from the deepest level up, each cell adding its
 // children in slot order starting from zero, so the FP64 sums are exactly
 // those of a recursive evaluation.
+#include <algorithm>
+
 #include "bh_device.h"
 
 namespace bh {
@@ -62,18 +64,33 @@ __global__ __launch_bounds__(256) void k_bbox_partial(const double *__restrict__
   if (threadIdx.x < 6) part[6 * (int64_t)blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ __launch_bounds__(64) void k_bbox_final(const double *__restrict__ part, int bps, SysInfo *sys) {
+__global__ __launch_bounds__(256) void k_bbox_final(const double *__restrict__ part, int bps, SysInfo *sys) {
+  __shared__ double red[6][256];
   const int s = blockIdx.x;
-  if (threadIdx.x != 0) return;
-  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int b = 0; b < bps; ++b)
+  double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int b = threadIdx.x; b < bps; b += blockDim.x)
     for (int k = 0; k < 3; ++k) {
-      lo[k] = fmin(lo[k], part[6 * ((int64_t)s * bps + b) + k]);
-      hi[k] = fmax(hi[k], part[6 * ((int64_t)s * bps + b) + 3 + k]);
+      mn[k] = fmin(mn[k], part[6 * ((int64_t)s * bps + b) + k]);
+      mx[k] = fmax(mx[k], part[6 * ((int64_t)s * bps + b) + 3 + k]);
     }
-  double ext = 0.0;
   for (int k = 0; k < 3; ++k) {
-    double e = hi[k] - lo[k];
+    red[k][threadIdx.x] = mn[k];
+    red[3 + k][threadIdx.x] = mx[k];
+  }
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int k = 0; k < 3; ++k) {
+        red[k][threadIdx.x] = fmin(red[k][threadIdx.x], red[k][threadIdx.x + w]);
+        red[3 + k][threadIdx.x] = fmax(red[3 + k][threadIdx.x], red[3 + k][threadIdx.x + w]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  double lo[3], ext = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = red[k][0];
+    const double e = red[3 + k][0] - red[k][0];
     if (e > ext) ext = e;
   }
   if (sys[s].count == 0 || !isfinite(ext)) {
@@ -81,7 +98,7 @@ __global__ __launch_bounds__(64) void k_bbox_final(const double *__restrict__ pa
     ext = 0.0;
   }
   // corner at the per-axis minimum, side = largest extent widened by 2^-20
-  double side = (ext > 0.0) ? __dmul_rn(ext, 1.0 + 0x1p-20) : 1.0;
+  const double side = (ext > 0.0) ? __dmul_rn(ext, 1.0 + 0x1p-20) : 1.0;
   for (int k = 0; k < 3; ++k) sys[s].lo[k] = lo[k];
   sys[s].side = side;
   sys[s].scale = 0x1p21 / side;
@@ -175,13 +192,13 @@ __global__ void k_owner(const uint64_t *__restrict__ keys, const int8_t *__restr
     const uint64_t kj = keys[j];
     if (d < kKeyLevels) {
       const int sh = prefix_shift(d);
-      int a = lower_bound_prefix(keys, lo, j, kj >> sh, sh);
+      int a = gallop_first(keys, lo, j, kj >> sh, sh);
       const int sh1 = prefix_shift(d + 1);
-      int e = upper_bound_prefix(keys, a, j + 1, keys[a] >> sh1, sh1);
+      int e = gallop_past(keys, a, j + 1, keys[a] >> sh1, sh1);
       own = e - 1;
       if (own == j) lev = d;
     } else {
-      own = lower_bound_prefix(keys, lo, j, kj, 0);
+      own = gallop_first(keys, lo, j, kj, 0);
       if (j == lo || delta[j - 1] != kKeyLevels) lev = kKeyLevels;
     }
   }
@@ -206,11 +223,11 @@ __global__ void k_cells(const uint64_t *__restrict__ keys, const int8_t *__restr
   int a, b;
   if (l < kKeyLevels) {
     const int sh = prefix_shift(l);
-    a = lower_bound_prefix(keys, lo, j, kj >> sh, sh);
-    b = upper_bound_prefix(keys, j, hi, kj >> sh, sh) - 1;
+    a = gallop_first(keys, lo, j, kj >> sh, sh);
+    b = gallop_past(keys, j, hi, kj >> sh, sh) - 1;
   } else {
     a = j;
-    b = upper_bound_prefix(keys, j, hi, kj, 0) - 1;
+    b = gallop_past(keys, j, hi, kj, 0) - 1;
   }
   cfirst[j] = a;
   ccount[j] = b - a + 1;
@@ -228,8 +245,6 @@ __global__ void k_cells(const uint64_t *__restrict__ keys, const int8_t *__restr
     cdigit[j] = (int8_t)dg;
     atomicOr(&mask[P], 1 << dg);
   }
-  atomicMax(&info->max_level, l);
-  atomicAdd(&info->n_cells, 1);
 }
 
 // Parent of every particle: a cell (octant mask updated), a bucket, or none
@@ -346,26 +361,106 @@ __global__ void k_empty_roots(const SysInfo *__restrict__ sys, int nsys, NodeRec
   for (int k = 0; k < 4; ++k) msum[4 * (int64_t)s + k] = 0.0;
 }
 
+// Cells grouped by level: counts, offsets, then a scatter (order within a
+// level is irrelevant: every cell sums its own children in slot order).
+// Lanes of a wave with the same level are found with ballots (peer masks), so
+// that LDS and global counters see one atomic per wave and level.
+__device__ __forceinline__ unsigned long long level_peers(int l) {
+  unsigned long long peers = __ballot(l >= 0);
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    const unsigned long long m = __ballot(l >= 0 && ((l >> b) & 1));
+    peers &= ((l >> b) & 1) ? m : ~m;
+  }
+  return (l >= 0) ? peers : 0ull;
+}
+
+constexpr int kLevelTile = 16;  // positions per thread in the level kernels
+
+__global__ __launch_bounds__(256) void k_level_count(const int8_t *__restrict__ level, int64_t n,
+                                                     int32_t *__restrict__ lcount) {
+  __shared__ int32_t c[kKeyLevels + 1];
+  if (threadIdx.x <= kKeyLevels) c[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x * kLevelTile;
+  for (int q = 0; q < kLevelTile; ++q) {
+    const int64_t j = base + (int64_t)q * blockDim.x + threadIdx.x;
+    const int l = (j < n) ? level[j] : -1;
+    const unsigned long long peers = level_peers(l);
+    if (l >= 0 && rank_below(peers) == 0) atomicAdd(&c[l], (int)__popcll(peers));
+  }
+  __syncthreads();
+  if (threadIdx.x <= kKeyLevels && c[threadIdx.x]) atomicAdd(&lcount[threadIdx.x], c[threadIdx.x]);
+}
+
+__global__ void k_level_offsets(const int32_t *__restrict__ lcount, int32_t *__restrict__ loff,
+                                int32_t *__restrict__ lcursor, DevInfo *info) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int32_t s = 0, deepest = 0;
+  for (int l = 0; l <= kKeyLevels; ++l) {
+    loff[l] = s;
+    lcursor[l] = s;
+    s += lcount[l];
+    if (lcount[l]) deepest = l;
+  }
+  loff[kKeyLevels + 1] = s;
+  info->n_cells = s;
+  info->max_level = deepest;
+}
+
+__global__ __launch_bounds__(256) void k_level_scatter(const int8_t *__restrict__ level, int64_t n,
+                                                       int32_t *__restrict__ lcursor, int32_t *__restrict__ lcells) {
+  // rank = block base (one global atomic per block and level) + wave base
+  // (one LDS atomic per wave, level and round) + lanes below with that level
+  __shared__ int32_t c[kKeyLevels + 1], base[kKeyLevels + 1];
+  if (threadIdx.x <= kKeyLevels) c[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t b0 = (int64_t)blockIdx.x * blockDim.x * kLevelTile;
+  int l[kLevelTile], pos[kLevelTile];
+  for (int q = 0; q < kLevelTile; ++q) {
+    const int64_t j = b0 + (int64_t)q * blockDim.x + threadIdx.x;
+    l[q] = (j < n) ? level[j] : -1;
+    const unsigned long long peers = level_peers(l[q]);
+    int wbase = 0;
+    if (l[q] >= 0 && rank_below(peers) == 0) wbase = atomicAdd(&c[l[q]], (int)__popcll(peers));
+    const int leader = (l[q] >= 0) ? (__ffsll((long long)peers) - 1) : 0;
+    wbase = __shfl(wbase, leader, kWave);
+    pos[q] = wbase + rank_below(peers);
+  }
+  __syncthreads();
+  if (threadIdx.x <= kKeyLevels && c[threadIdx.x]) base[threadIdx.x] = atomicAdd(&lcursor[threadIdx.x], c[threadIdx.x]);
+  __syncthreads();
+  for (int q = 0; q < kLevelTile; ++q) {
+    const int64_t j = b0 + (int64_t)q * blockDim.x + threadIdx.x;
+    if (l[q] >= 0) lcells[base[l[q]] + pos[q]] = (int32_t)j;
+  }
+}
+
+__global__ void k_zero_levels(int32_t *__restrict__ lcount) {
+  if (threadIdx.x <= kKeyLevels && blockIdx.x == 0) lcount[threadIdx.x] = 0;
+}
+
 // Moments of the cells of one level from their children's raw sums.
-__global__ void k_moments(int lev, const int8_t *__restrict__ level, const int32_t *__restrict__ cparent,
+__global__ void k_moments(int lev, const int32_t *__restrict__ lcells, const int32_t *__restrict__ loff,
+                          const int8_t *__restrict__ level, const int32_t *__restrict__ cparent,
                           const int32_t *__restrict__ cslot,
                           const int32_t *__restrict__ cfc, const int32_t *__restrict__ nchild,
                           const int32_t *__restrict__ cfirst, const int32_t *__restrict__ ccount,
                           const uint64_t *__restrict__ keys, const SysInfo *__restrict__ sys, int nsys, int64_t n,
                           int64_t cap, NodeRec *__restrict__ nodes, double *__restrict__ msum,
                           int8_t *__restrict__ meta, DevInfo *info) {
-  int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (jj >= n) return;
-  const int j = (int)jj;
-  if (level[j] != lev) return;
+  const int64_t end = loff[lev + 1];
+  for (int64_t k = (int64_t)loff[lev] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < end;
+       k += (int64_t)gridDim.x * blockDim.x) {
+  const int j = lcells[k];
   const int c0 = nsys + cfc[j], nc = nchild[j];
   if (c0 < 0 || nc < 0 || (int64_t)c0 + nc > cap || cslot[j] < 0 || cslot[j] >= cap) {
     atomicOr(&info->err, kErrBuild);
-    return;
+    continue;
   }
   double m = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
-  for (int k = 0; k < nc; ++k) {
-    const double *q = msum + 4 * (int64_t)(c0 + k);
+  for (int ci = 0; ci < nc; ++ci) {
+    const double *q = msum + 4 * (int64_t)(c0 + ci);
     m = __dadd_rn(m, q[0]);
     mx = __dadd_rn(mx, q[1]);
     my = __dadd_rn(my, q[2]);
@@ -415,6 +510,7 @@ __global__ void k_moments(int lev, const int8_t *__restrict__ level, const int32
   r.count = ccount[j];
   nodes[slot] = r;
   meta[slot] = (int8_t)(lev == kKeyLevels ? 32 * kBucket + lev : lev);
+  }
 }
 
 inline unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
@@ -437,7 +533,7 @@ void build_tree_device(TreeBuffers &B, hipStream_t s) {
   const int nsys = B.nsys;
   const int bps = bbox_blocks_per_system(nsys);
   k_bbox_partial<<<(unsigned)(nsys * bps), 256, 0, s>>>(B.pos, B.sys, bps, B.bbox_part, B.info);
-  k_bbox_final<<<(unsigned)nsys, 64, 0, s>>>(B.bbox_part, bps, B.sys);
+  k_bbox_final<<<(unsigned)nsys, 256, 0, s>>>(B.bbox_part, bps, B.sys);
   if (n == 0) {
     B.sorted_keys = B.keys[0];
     k_empty_roots<<<blocks_for(nsys), 256, 0, s>>>(B.sys, nsys, B.nodes, B.msum, B.meta);
@@ -467,9 +563,16 @@ void build_tree_device(TreeBuffers &B, hipStream_t s) {
   k_slots<<<blocks_for(n), 256, 0, s>>>(B.level, B.cparent, B.cdigit, B.pparent, B.pdigit, B.cfc, B.mask, B.spos,
                                          B.smass, n, nsys, B.slot_cap, B.cslot, B.nodes, B.msum, B.meta, B.info);
   k_empty_roots<<<blocks_for(nsys), 256, 0, s>>>(B.sys, nsys, B.nodes, B.msum, B.meta);
+  k_zero_levels<<<1, 64, 0, s>>>(B.lcount);
+  k_level_count<<<blocks_for(n, 256 * kLevelTile), 256, 0, s>>>(B.level, n, B.lcount);
+  k_level_offsets<<<1, 64, 0, s>>>(B.lcount, B.loff, B.lcursor, B.info);
+  k_level_scatter<<<blocks_for(n, 256 * kLevelTile), 256, 0, s>>>(B.level, n, B.lcursor, B.lcells);
+  const unsigned mgrid = (unsigned)std::min<int64_t>(blocks_for(n), 512);
   for (int lev = kKeyLevels; lev >= 0; --lev)
-    k_moments<<<blocks_for(n), 256, 0, s>>>(lev, B.level, B.cparent, B.cslot, B.cfc, B.nchild, B.cfirst, B.ccount,
-                                             keys, B.sys, nsys, n, B.slot_cap, B.nodes, B.msum, B.meta, B.info);
+    k_moments<<<mgrid, 256, 0, s>>>(lev, B.lcells, B.loff, B.level, B.cparent,
+                                                                        B.cslot, B.cfc, B.nchild, B.cfirst, B.ccount,
+                                                                        keys, B.sys, nsys, n, B.slot_cap, B.nodes,
+                                                                        B.msum, B.meta, B.info);
 }
 
 }  // namespace bh
