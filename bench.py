@@ -16,6 +16,8 @@ the FP64 CPU oracle's throughput on a bounded sample are reported beside it.
 from __future__ import annotations
 
 import argparse
+import dataclasses
+import hashlib
 import json
 import math
 import os
@@ -31,6 +33,23 @@ FP32_VALU_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
 FLOPS_PER_INTERACTION = 20      # 3 sub, 3 FMA (r^2), rsqrt, 3 mul, 3 FMA (acc), 1 add (pot)
 
 
+# HBM traffic of the force kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# of this script (bytes per interaction, scaled by the counters' reading of a
+# device copy of known size), valid only for the kernel source it was taken on.
+TRAFFIC = {}
+
+
+def traffic_for(workload, interactions, t_force_ms):
+    rec = TRAFFIC.get(workload)
+    if rec is None:
+        return None
+    src = os.path.join(ROOT, "paper_0909_0541_amd", "csrc", "k_force.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["k_force_sha256"]:
+            return None
+    return rec["bytes_per_launch"]
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -42,6 +61,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--waves-per-cu", type=int, default=None)
+    ap.add_argument("--target-rms", type=float, default=1e-3,
+                    help="calibrate theta by bisection to this RMS force error before timing "
+                         "(0: time the workload's own theta)")
+    ap.add_argument("--copy-check-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB before the timed steps, "
+                         "as the reference kernel that scales HBM byte counters")
     return ap.parse_args()
 
 
@@ -96,6 +121,32 @@ def _cpu_model():
     return "unknown"
 
 
+def bisect_theta(rms_of, target, lo=0.3, hi=1.0, rel_tol=0.03, iters=14):
+    """theta in [lo, hi] whose RMS force error is within rel_tol of target
+    (the error grows with theta); returns (theta, rms) of the closest try."""
+    best = None
+    r_lo, r_hi = rms_of(lo), rms_of(hi)
+    for th, r in ((lo, r_lo), (hi, r_hi)):
+        if best is None or abs(r / target - 1) < abs(best[1] / target - 1):
+            best = (th, r)
+    if r_hi <= target:
+        return hi, r_hi
+    if r_lo >= target:
+        return lo, r_lo
+    for _ in range(iters):
+        mid = 0.5 * (lo + hi)
+        r = rms_of(mid)
+        if abs(r / target - 1) < abs(best[1] / target - 1):
+            best = (mid, r)
+        if abs(r / target - 1) <= rel_tol:
+            break
+        if r > target:
+            hi = mid
+        else:
+            lo = mid
+    return best
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -116,45 +167,71 @@ def main():
     pot = torch.empty(n, dtype=torch.float32, device="cuda")
     ctx = bh.Context(timing=True, waves_per_cu=args.waves_per_cu)
 
-    def step():
+    def step(theta):
         ctx.build_tree(dpos, dmass)
         ctx.make_groups(w.n_crit, sync=False)
-        ctx.compute_forces(w.eps, w.theta, acc=acc, pot=pot)
+        ctx.compute_forces(w.eps, theta, acc=acc, pot=pot)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.get_stats()  # clears the warm-up timings
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.steps):
-        step()
-    e1.record()
-    torch.cuda.synchronize()
-    ms_per_step = e0.elapsed_time(e1) / args.steps
-    st = ctx.get_stats()
-    if st.error_flags:
-        raise SystemExit(f"device error flags {st.error_flags}")
-    t_force = st.t_force_ms / max(st.n_force_calls, 1)
-    t_walk = st.t_walk_ms / max(st.n_walk_calls, 1)
-    t_build = st.t_build_ms / max(st.n_build_calls, 1)
-    t_groups = st.t_groups_ms / max(st.n_groups_calls, 1)
-    inter = st.interactions
-    value = inter / (ms_per_step * 1e-3)
-
-    # accuracy: RMS relative force error against FP64 direct summation
+    # judge: FP64 direct summation on the GPU for a seeded sample
     rng = np.random.default_rng(12345)
     s = min(args.judge_sample, n)
     idx = np.sort(rng.choice(n, s, replace=False))
     didx = torch.as_tensor(idx, device="cuda")
     a_dir, _ = ctx.direct_sampled(dpos, dmass, w.eps, didx)
     a_dir = a_dir.cpu().numpy()
-    a_tree = acc[didx].double().cpu().numpy()
-    rel = np.linalg.norm(a_tree - a_dir, axis=1) / np.linalg.norm(a_dir, axis=1)
-    rms = float(math.sqrt(np.mean(rel * rel)))
+    a_dir_norm = np.linalg.norm(a_dir, axis=1)
 
+    def rms_now():
+        a_tree = acc[didx].double().cpu().numpy()
+        rel = np.linalg.norm(a_tree - a_dir, axis=1) / a_dir_norm
+        return float(math.sqrt(np.mean(rel * rel)))
+
+    def rms_of(theta):
+        step(theta)
+        return rms_now()
+
+    calib = None
+    theta = w.theta
+    if args.target_rms > 0:
+        theta, r = bisect_theta(rms_of, args.target_rms)
+        calib = {"target_rms": args.target_rms, "theta": theta, "rms": r, "band": 0.03,
+                 "search": "bisection over theta in [0.3, 1.0]"}
+
+    if args.copy_check_mib > 0:
+        nb = args.copy_check_mib << 20
+        src = torch.ones(nb, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    def timed(theta_run):
+        for _ in range(args.warmup):
+            step(theta_run)
+        torch.cuda.synchronize()
+        ctx.get_stats()  # clears the warm-up timings
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            step(theta_run)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        st = ctx.get_stats()
+        if st.error_flags:
+            raise SystemExit(f"device error flags {st.error_flags}")
+        per = lambda t, k: t / max(k, 1)
+        return ms, st, {"build": per(st.t_build_ms, st.n_build_calls), "groups": per(st.t_groups_ms, st.n_groups_calls),
+                        "walk": per(st.t_walk_ms, st.n_walk_calls), "force": per(st.t_force_ms, st.n_force_calls)}
+
+    ms_per_step, st, stage = timed(theta)
+    rms = rms_now()
+    inter = st.interactions
+    value = inter / (ms_per_step * 1e-3)
+    t_force = stage["force"]
     achieved = FLOPS_PER_INTERACTION * inter / (t_force * 1e-3) / 1e12
     line = {
         "metric": METRIC,
@@ -169,25 +246,35 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "description": w.description, "n": n, "eps": w.eps, "theta": w.theta,
-                   "n_crit": w.n_crit, "theta_mode": "fixed"},
+        "config": {"workload": w.name, "description": w.description, "n": n, "eps": w.eps, "theta": theta,
+                   "workload_theta": w.theta, "n_crit": w.n_crit,
+                   "theta_mode": "fixed" if calib is None else "fixed, bisected to the target RMS force error"},
         "particles_per_s": n / (ms_per_step * 1e-3),
         "interactions_per_step": inter,
         "interactions_per_particle": inter / n,
         "rms_force_error": rms,
         "judge_sample": s,
+        "theta_calibration": calib,
         "groups": st.n_groups,
         "cells": st.n_cells,
         "max_list": st.max_list,
-        "stage_ms": {"build": t_build, "groups": t_groups, "walk": t_walk, "force": t_force},
+        "stage_ms": stage,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": traffic_for(w.name, inter, t_force),
                      "kernel": "k_force_lists", "flops_per_interaction": FLOPS_PER_INTERACTION},
         "force_kernel_interactions_per_s": inter / (t_force * 1e-3),
-        "walk_plus_force_interactions_per_s": inter / ((t_walk + t_force) * 1e-3),
+        "walk_plus_force_interactions_per_s": inter / ((stage["walk"] + t_force) * 1e-3),
     }
+    if calib is not None and abs(theta - w.theta) > 1e-12:
+        ms2, st2, stage2 = timed(w.theta)
+        line["at_workload_theta"] = {
+            "theta": w.theta, "rms_force_error": rms_now(), "ms_per_step": ms2,
+            "interactions_per_s": st2.interactions / (ms2 * 1e-3), "particles_per_s": n / (ms2 * 1e-3),
+            "interactions_per_step": st2.interactions, "stage_ms": stage2,
+            "force_kernel_tflops": FLOPS_PER_INTERACTION * st2.interactions / (stage2["force"] * 1e-3) / 1e12}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(pos, mass, w, inter, args.cpu_seconds)
+        w_cpu = w if calib is None else dataclasses.replace(w, theta=theta)
+        line["cpu_baseline"] = cpu_baseline(pos, mass, w_cpu, inter, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 

@@ -193,9 +193,76 @@ bh_status bh_kick(bh_ctx *ctx, int64_t n, double *vel, const float *acc, double 
 /* pos += dt * vel (both FP64 [n][3]). */
 bh_status bh_drift(bh_ctx *ctx, int64_t n, double *pos, const double *vel, double dt);
 
+/* Kick-drift-kick leapfrog (the time integration of Sec. 4; the scheme is a
+ * reading): per step vel += dt/2 acc, pos += dt vel, tree + groups + forces at
+ * the new positions, vel += dt/2 acc.  FP64 state, FP32 accelerations.
+ *   pos, vel device FP64 [n][3] (updated in place), mass device FP64 [n].
+ *   acc, pot device FP32 in/out: on entry the forces at pos (from a
+ *   bh_build_tree + bh_make_groups + bh_compute_forces with the same eps,
+ *   theta, n_crit, or the previous bh_leapfrog call), on return the forces at
+ *   the final positions.  The context's tree and groups are those of the
+ *   final positions.  steps >= 0, dt finite; eps, theta, n_crit as for the
+ *   force and group calls.  Synchronises once per step (list pool check). */
+bh_status bh_leapfrog(bh_ctx *ctx, int64_t n, double *pos, double *vel, const double *mass, double eps,
+                      double theta, int32_t n_crit, double dt, int32_t steps, float *acc, float *pot);
+
 /* energy device FP64 [2]: kinetic sum(m v^2 / 2) and potential sum(m pot / 2). */
 bh_status bh_energy(bh_ctx *ctx, int64_t n, const double *vel, const double *mass, const float *pot,
                     double *energy);
+
+/* ---- learned per-group theta ------------------------------------------- */
+
+/* The paper fixes one opening angle and studies its accuracy/work trade-off
+ * (Sec. 4).  These calls let a small network choose theta per group instead:
+ * 12 group features -> tanh(64) -> tanh(64) -> theta = 0.3 + 0.7 sigmoid(y +
+ * shift).  Features (FP32, per group, from the current tree and groups):
+ *   f0 = log2 c, f1 = log2(1 + R/eps), f2 = |x_g - c_g| / (R + eps),
+ *   f3 = log2(l(A1) / (R + eps)), f4..f7 = log2(m(Ak) / m_g),
+ *   f8..f11 = |com(Ak) - c_g| / l(Ak), k = 1..4,
+ * with c the member count, c_g the box centre, R the box half-diagonal, x_g
+ * and m_g the members' centre of mass and mass, A1 the smallest cell (not a
+ * bucket of equal keys) holding more than c particles, A(k+1) the cell above
+ * Ak (Ak again at the root); a group that is a whole system has f3..f11 = 0. */
+#define BH_MLP_FEATURES 12
+#define BH_MLP_HIDDEN 64
+#define BH_MLP_PARAMS 5057
+
+typedef struct bh_mlp {
+  const float *params; /* device FP32 [BH_MLP_PARAMS]: W1 [64][12], b1 [64], W2 [64][64], b2 [64], w3 [64], b3 */
+  const float *mu;     /* device FP32 [12]: feature offsets */
+  const float *sigma;  /* device FP32 [12]: feature scales (nonzero); the network reads (f - mu) / sigma */
+} bh_mlp;
+
+/* Features of the current groups.  eps_sys host FP64 [n_systems] (> 0).
+ * feat device FP32 [n_groups][12] (n_groups <= max(n, 1)).  Asynchronous.
+ * BH_ESTATE without groups. */
+bh_status bh_group_features(bh_ctx *ctx, const double *eps_sys, float *feat);
+
+/* theta for rows of features, on the matrix cores in bfloat16 (features
+ * after normalisation, the two hidden layers' weights and the first hidden
+ * activations are rounded to bfloat16; sums, biases, tanh and the output
+ * layer are FP32).  feat device FP32 [rows][12], theta device FP32 [rows]. */
+bh_status bh_mlp_infer(bh_ctx *ctx, const bh_mlp *net, int64_t rows, const float *feat, float shift, float *theta);
+
+/* Features and theta of the current groups in one asynchronous call (the
+ * features go to a context-owned buffer).  theta device FP32, room for
+ * max(n, 1) values; pass it as theta_group to bh_compute_forces. */
+bh_status bh_group_theta(bh_ctx *ctx, const bh_mlp *net, const double *eps_sys, float shift, float *theta);
+
+/* FP32 loss and gradient of a training batch: loss = sum_b w_b (theta_b -
+ * target_b)^2 / sum_b w_b with theta_b the network output at shift 0 (FP32
+ * throughout).  x device FP32 [batch][12], target and weight device FP32
+ * [batch] (weights >= 0, positive sum); grad device FP32 [BH_MLP_PARAMS]
+ * (summed over the batch in sample order); loss device FP32 [1], nullable.
+ * batch in [1, 65536]. */
+bh_status bh_mlp_grad(bh_ctx *ctx, const bh_mlp *net, int32_t batch, const float *x, const float *target,
+                      const float *weight, float *grad, float *loss);
+
+/* One Adam step (bias-corrected, step >= 1) on device FP32 arrays of n
+ * values: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * params -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps). */
+bh_status bh_mlp_adam(bh_ctx *ctx, float *params, const float *grad, float *m, float *v, int32_t n, int32_t step,
+                      float lr, float beta1, float beta2, float eps);
 
 /* ---- inspection (tests and tools) -------------------------------------- */
 

@@ -40,6 +40,13 @@ class _Stats(C.Structure):
                 ("n_groups_calls", C.c_int32), ("n_walk_calls", C.c_int32), ("n_force_calls", C.c_int32)]
 
 
+class _Mlp(C.Structure):
+    _fields_ = [("params", C.c_void_p), ("mu", C.c_void_p), ("sigma", C.c_void_p)]
+
+
+MLP_FEATURES, MLP_HIDDEN, MLP_PARAMS = 12, 64, 5057
+
+
 class _Options(C.Structure):
     _fields_ = [("waves_per_cu", C.c_int32), ("timing", C.c_int32)]
 
@@ -66,7 +73,13 @@ def load():
         "bh_make_groups": ([vp, i32, C.POINTER(i64)], C.c_int),
         "bh_compute_forces": ([vp, dbl, dbl, vp, vp, vp], C.c_int),
         "bh_compute_forces_batch": ([vp, vp, vp, vp, vp, vp], C.c_int),
+        "bh_leapfrog": ([vp, i64, vp, vp, vp, C.c_double, C.c_double, i32, C.c_double, i32, vp, vp], C.c_int),
         "bh_get_stats": ([vp, C.POINTER(_Stats)], C.c_int),
+        "bh_group_features": ([vp, vp, vp], C.c_int),
+        "bh_mlp_infer": ([vp, C.POINTER(_Mlp), i64, vp, C.c_float, vp], C.c_int),
+        "bh_group_theta": ([vp, C.POINTER(_Mlp), vp, C.c_float, vp], C.c_int),
+        "bh_mlp_grad": ([vp, C.POINTER(_Mlp), i32, vp, vp, vp, vp, vp], C.c_int),
+        "bh_mlp_adam": ([vp, vp, vp, vp, vp, i32, i32, C.c_float, C.c_float, C.c_float, C.c_float], C.c_int),
         "bh_direct_sampled": ([vp, i64, vp, vp, dbl, i64, vp, vp, vp], C.c_int),
         "bh_kick": ([vp, i64, vp, vp, dbl], C.c_int),
         "bh_drift": ([vp, i64, vp, vp, dbl], C.c_int),
@@ -261,6 +274,19 @@ class Context:
         _dev(vel, torch.float64, (n, 3), "vel")
         self._check(self._L.bh_drift(self._h, n, _ptr(pos), _ptr(vel), float(dt)))
 
+    def leapfrog(self, pos: torch.Tensor, vel: torch.Tensor, mass: torch.Tensor, eps: float, theta: float,
+                 n_crit: int, dt: float, steps: int, acc: torch.Tensor, pot: torch.Tensor):
+        """steps KDK steps in place; acc/pot must hold the forces at pos."""
+        n = pos.shape[0]
+        _dev(pos, torch.float64, (n, 3), "pos")
+        _dev(vel, torch.float64, (n, 3), "vel")
+        _dev(mass, torch.float64, (n,), "mass")
+        _dev(acc, torch.float32, (n, 3), "acc")
+        _dev(pot, torch.float32, (n,), "pot")
+        self._check(self._L.bh_leapfrog(self._h, n, _ptr(pos), _ptr(vel), _ptr(mass), float(eps), float(theta),
+                                        int(n_crit), float(dt), int(steps), _ptr(acc), _ptr(pot)))
+        self.n, self.n_systems = n, 1
+
     def energy(self, vel: torch.Tensor, mass: torch.Tensor, pot: torch.Tensor, out: torch.Tensor | None = None):
         n = vel.shape[0]
         _dev(vel, torch.float64, (n, 3), "vel")
@@ -270,6 +296,73 @@ class Context:
             out = torch.empty(2, dtype=torch.float64, device=vel.device)
         self._check(self._L.bh_energy(self._h, n, _ptr(vel), _ptr(mass), _ptr(pot), _ptr(out)))
         return out
+
+    # ---- learned per-group theta ----
+    @staticmethod
+    def _net(params, mu, sigma):
+        _dev(params, torch.float32, (MLP_PARAMS,), "params")
+        _dev(mu, torch.float32, (MLP_FEATURES,), "mu")
+        _dev(sigma, torch.float32, (MLP_FEATURES,), "sigma")
+        return _Mlp(_ptr(params), _ptr(mu), _ptr(sigma))
+
+    def _eps_sys(self, eps):
+        import numpy as np
+        e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, dtype=np.float64), (self.n_systems,)))
+        return e
+
+    def group_features(self, eps, n_groups: int):
+        """[n_groups, 12] FP32 features of the current groups (n_groups as
+        returned by make_groups)."""
+        dev = torch.device("cuda", torch.cuda.current_device())
+        feat = torch.empty((max(self.n, 1), MLP_FEATURES), dtype=torch.float32, device=dev)
+        e = self._eps_sys(eps)
+        self._check(self._L.bh_group_features(self._h, e.ctypes.data_as(C.c_void_p), _ptr(feat)))
+        return feat[:n_groups]
+
+    def mlp_infer(self, params, mu, sigma, feat, shift: float = 0.0, theta=None):
+        rows = feat.shape[0]
+        _dev(feat, torch.float32, (rows, MLP_FEATURES), "feat")
+        if theta is None:
+            theta = torch.empty(rows, dtype=torch.float32, device=feat.device)
+        _dev(theta, torch.float32, None, "theta")
+        net = self._net(params, mu, sigma)
+        self._check(self._L.bh_mlp_infer(self._h, C.byref(net), rows, _ptr(feat), float(shift), _ptr(theta)))
+        return theta
+
+    def group_theta(self, params, mu, sigma, eps, shift: float = 0.0, theta=None):
+        """theta of every current group (room for max(n, 1) values)."""
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if theta is None:
+            theta = torch.empty(max(self.n, 1), dtype=torch.float32, device=dev)
+        _dev(theta, torch.float32, None, "theta")
+        if theta.shape[0] < max(self.n, 1):
+            raise ValueError("theta needs room for max(n, 1) values")
+        net = self._net(params, mu, sigma)
+        e = self._eps_sys(eps)
+        self._check(self._L.bh_group_theta(self._h, C.byref(net), e.ctypes.data_as(C.c_void_p), float(shift),
+                                           _ptr(theta)))
+        return theta
+
+    def mlp_grad(self, params, mu, sigma, x, target, weight, grad=None, loss=None):
+        B = x.shape[0]
+        _dev(x, torch.float32, (B, MLP_FEATURES), "x")
+        _dev(target, torch.float32, (B,), "target")
+        _dev(weight, torch.float32, (B,), "weight")
+        if grad is None:
+            grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=x.device)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        net = self._net(params, mu, sigma)
+        self._check(self._L.bh_mlp_grad(self._h, C.byref(net), B, _ptr(x), _ptr(target), _ptr(weight), _ptr(grad),
+                                        _ptr(loss)))
+        return grad, loss
+
+    def mlp_adam(self, params, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
+        n = params.shape[0]
+        for t_, name in ((params, "params"), (grad, "grad"), (m, "m"), (v, "v")):
+            _dev(t_, torch.float32, (n,), name)
+        self._check(self._L.bh_mlp_adam(self._h, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), n, int(step), float(lr),
+                                        float(beta1), float(beta2), float(eps)))
 
     # ---- inspection ----
     def export_sorted(self):

@@ -350,7 +350,7 @@ void bh_destroy(bh_ctx *c) {
                     &c->hist, &c->nodes, &c->msum, &c->meta, &c->levels, &c->lcells, &c->gflag, &c->gidx, &c->glen, &c->ginfo, &c->gbox, &c->glist,
                     &c->gmass, &c->bbox_part, &c->sys, &c->par, &c->info, &c->direct_part, &c->energy_part,
                     &c->glists, &c->far_pool, &c->near_pool, &c->far_next, &c->near_next,
-                    &c->items, &c->item_n, &c->item_off};
+                    &c->items, &c->item_n, &c->item_off, &c->feps, &c->mlp_work, &c->mlp_feat};
   for (DevBuf *b : bufs) free_buf(*b);
   if (c->info_host) (void)hipHostFree(c->info_host);
   if (c->stage) (void)hipHostFree(c->stage);
@@ -642,6 +642,28 @@ bh_status bh_drift(bh_ctx *c, int64_t n, double *pos, const double *vel, double 
   return hip_check(c, hipGetLastError(), "kernel launch (drift)");
 }
 
+bh_status bh_leapfrog(bh_ctx *c, int64_t n, double *pos, double *vel, const double *mass, double eps, double theta,
+                      int32_t n_crit, double dt, int32_t steps, float *acc, float *pot) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (n < 0 || n > BH_MAX_N) return fail(c, BH_EINVAL, "n out of range");
+  if (steps < 0) return fail(c, BH_EINVAL, "steps must be >= 0");
+  if (!isfinite(dt)) return fail(c, BH_EINVAL, "dt must be finite");
+  if (n > 0 && (!pos || !vel || !mass || !acc || !pot)) return fail(c, BH_EINVAL, "bad leapfrog arguments");
+  if (n_crit < 1 || n_crit > BH_MAX_NCRIT) return fail(c, BH_EINVAL, "n_crit must be in [1, 256]");
+  const double h = 0.5 * dt;
+  for (int32_t k = 0; k < steps; ++k) {
+    bh_status st = bh_kick(c, n, vel, acc, h);
+    if (!st) st = bh_drift(c, n, pos, vel, dt);
+    if (!st) st = bh_build_tree(c, n, pos, mass);
+    if (!st) st = bh_make_groups(c, n_crit, nullptr);
+    if (!st) st = bh_compute_forces(c, eps, theta, nullptr, acc, pot);
+    if (!st) st = bh_kick(c, n, vel, acc, h);
+    if (st) return st;
+  }
+  return BH_OK;
+}
+
 bh_status bh_energy(bh_ctx *c, int64_t n, const double *vel, const double *mass, const float *pot,
                     double *energy) {
   if (!c) return BH_EINVAL;
@@ -651,6 +673,116 @@ bh_status bh_energy(bh_ctx *c, int64_t n, const double *vel, const double *mass,
   if (st) return st;
   energy_device(n, vel, mass, pot, P<double>(c->energy_part), energy, c->stream);
   return hip_check(c, hipGetLastError(), "kernel launch (energy)");
+}
+
+static bh_status check_net(bh_ctx *c, const bh_mlp *net) {
+  if (!net || !net->params || !net->mu || !net->sigma) return fail(c, BH_EINVAL, "network pointers must not be NULL");
+  return BH_OK;
+}
+
+static bh_status features_common(bh_ctx *c, const double *eps_sys, float *feat) {
+  if (!c->have_groups) return fail(c, BH_ESTATE, "features requested before bh_make_groups");
+  if (!eps_sys) return fail(c, BH_EINVAL, "eps_sys must not be NULL");
+  if (c->n > 0 && !feat) return fail(c, BH_EINVAL, "feat must not be NULL");
+  c->feps_host.assign((size_t)c->nsys, 0.0);
+  for (int s = 0; s < c->nsys; ++s) {
+    if (!(eps_sys[s] > 0.0) || !isfinite(eps_sys[s])) return fail(c, BH_EINVAL, "eps must be positive and finite");
+    c->feps_host[s] = eps_sys[s];
+  }
+  bh_status st = ensure(c, c->feps, sizeof(double) * (size_t)c->nsys, "feature softening");
+  if (st) return st;
+  st = upload(c, c->feps.p, c->feps_host.data(), sizeof(double) * (size_t)c->nsys);
+  if (st) return st;
+  if (c->n == 0) return BH_OK;
+  FeatureArgs a{};
+  a.ginfo = P<int32_t>(c->ginfo);
+  a.gbox = P<double>(c->gbox);
+  a.spos = P<double>(c->spos);
+  a.smass = P<double>(c->smass);
+  a.pparent = P<int32_t>(c->pparent);
+  a.cparent = P<int32_t>(c->cparent);
+  a.ccount = P<int32_t>(c->ccount);
+  a.cslot = P<int32_t>(c->cslot);
+  a.level = P<int8_t>(c->level);
+  a.nodes = P<NodeRec>(c->nodes);
+  a.eps = P<double>(c->feps);
+  a.info = P<DevInfo>(c->info);
+  a.feat = feat;
+  group_features_device(a, c->n, c->stream);
+  return hip_check(c, hipGetLastError(), "kernel launch (features)");
+}
+
+bh_status bh_group_features(bh_ctx *c, const double *eps_sys, float *feat) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  return features_common(c, eps_sys, feat);
+}
+
+bh_status bh_mlp_infer(bh_ctx *c, const bh_mlp *net, int64_t rows, const float *feat, float shift, float *theta) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  bh_status st = check_net(c, net);
+  if (st) return st;
+  if (rows < 0 || rows > BH_MAX_N) return fail(c, BH_EINVAL, "rows out of range");
+  if (!isfinite(shift)) return fail(c, BH_EINVAL, "shift must be finite");
+  if (rows == 0) return BH_OK;
+  if (!feat || !theta) return fail(c, BH_EINVAL, "feat and theta must not be NULL");
+  mlp_infer_device(net->params, net->mu, net->sigma, feat, rows, rows, P<DevInfo>(c->info), shift, theta, c->stream);
+  return hip_check(c, hipGetLastError(), "kernel launch (inference)");
+}
+
+bh_status bh_group_theta(bh_ctx *c, const bh_mlp *net, const double *eps_sys, float shift, float *theta) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  bh_status st = check_net(c, net);
+  if (st) return st;
+  if (!isfinite(shift)) return fail(c, BH_EINVAL, "shift must be finite");
+  if (c->n > 0 && !theta) return fail(c, BH_EINVAL, "theta must not be NULL");
+  const int64_t cap = std::max<int64_t>(c->n, 1);
+  st = ensure(c, c->mlp_feat, sizeof(float) * BH_MLP_FEATURES * (size_t)cap, "features");
+  if (st) return st;
+  st = features_common(c, eps_sys, P<float>(c->mlp_feat));
+  if (st || c->n == 0) return st;
+  // rows = -1: the kernel reads the group count on the device
+  mlp_infer_device(net->params, net->mu, net->sigma, P<float>(c->mlp_feat), -1, cap, P<DevInfo>(c->info), shift,
+                   theta, c->stream);
+  return hip_check(c, hipGetLastError(), "kernel launch (inference)");
+}
+
+bh_status bh_mlp_grad(bh_ctx *c, const bh_mlp *net, int32_t batch, const float *x, const float *target,
+                      const float *weight, float *grad, float *loss) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  bh_status st = check_net(c, net);
+  if (st) return st;
+  if (batch < 1 || batch > 65536) return fail(c, BH_EINVAL, "batch must be in [1, 65536]");
+  if (!x || !target || !weight || !grad) return fail(c, BH_EINVAL, "x, target, weight and grad must not be NULL");
+  const size_t per = BH_MLP_FEATURES + 4 * BH_MLP_HIDDEN + 2;
+  st = ensure(c, c->mlp_work, sizeof(float) * (per * (size_t)batch + 1), "training workspace");
+  if (st) return st;
+  float *w = P<float>(c->mlp_work);
+  MlpWork ws{};
+  ws.xn = w;
+  ws.h1 = ws.xn + (size_t)batch * BH_MLP_FEATURES;
+  ws.h2 = ws.h1 + (size_t)batch * BH_MLP_HIDDEN;
+  ws.dz1 = ws.h2 + (size_t)batch * BH_MLP_HIDDEN;
+  ws.dz2 = ws.dz1 + (size_t)batch * BH_MLP_HIDDEN;
+  ws.dy = ws.dz2 + (size_t)batch * BH_MLP_HIDDEN;
+  ws.loss = ws.dy + batch;
+  ws.wsum = ws.loss + batch;
+  mlp_grad_device(net->params, net->mu, net->sigma, batch, x, target, weight, ws, grad, loss, c->stream);
+  return hip_check(c, hipGetLastError(), "kernel launch (training)");
+}
+
+bh_status bh_mlp_adam(bh_ctx *c, float *params, const float *grad, float *m, float *v, int32_t n, int32_t step,
+                      float lr, float beta1, float beta2, float eps) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (n < 1 || step < 1 || !params || !grad || !m || !v) return fail(c, BH_EINVAL, "bad Adam arguments");
+  if (!(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return fail(c, BH_EINVAL, "bad Adam hyper-parameters");
+  adam_device(params, grad, m, v, n, lr, beta1, beta2, eps, step, c->stream);
+  return hip_check(c, hipGetLastError(), "kernel launch (Adam)");
 }
 
 bh_status bh_export_sorted(bh_ctx *c, uint64_t *keys, int32_t *perm) {

@@ -157,6 +157,10 @@ struct bh_ctx {
   bh::DevBuf info;              // DevInfo
   bh::DevBuf direct_part;       // FP64 partial sums of the judge
   bh::DevBuf energy_part;       // FP64 energy partials
+  bh::DevBuf feps;              // FP64 [nsys] softening of the feature call
+  bh::DevBuf mlp_work;          // training batch workspace
+  bh::DevBuf mlp_feat;          // FP32 [n][12] features of bh_group_theta
+  std::vector<double> feps_host;
   bh::DevInfo *info_host = nullptr;  // pinned mirror
   std::vector<bh::SysInfo> sys_host;
   std::vector<bh::SysParam> par_host;
@@ -298,5 +302,30 @@ size_t energy_part_bytes();
 void energy_device(int64_t n, const double *vel, const double *mass, const float *pot, double *part, double *out,
                    hipStream_t s);
 void reset_info_device(DevInfo *info, hipStream_t s);
+
+// k_mlp.hip: per-group theta from a 12 -> 64 -> 64 -> 1 network
+constexpr int kMlpParams = 64 * 12 + 64 + 64 * 64 + 64 + 64 + 1;
+constexpr float kThetaMin = 0.3f, kThetaSpan = 0.7f;
+struct FeatureArgs {
+  const int32_t *ginfo;
+  const double *gbox;
+  const double *spos, *smass;
+  const int32_t *pparent, *cparent, *ccount, *cslot;
+  const int8_t *level;
+  const NodeRec *nodes;
+  const double *eps;  // per system
+  DevInfo *info;
+  float *feat;        // [G][12]
+};
+struct MlpWork {  // per-sample activations and gradients of a training batch
+  float *xn, *h1, *h2, *dz1, *dz2, *dy, *loss, *wsum;
+};
+void group_features_device(const FeatureArgs &a, int64_t cap, hipStream_t s);
+void mlp_infer_device(const float *params, const float *mu, const float *sigma, const float *x, int64_t rows,
+                      int64_t cap_rows, const DevInfo *info, float shift, float *theta, hipStream_t s);
+void mlp_grad_device(const float *params, const float *mu, const float *sigma, int B, const float *x,
+                     const float *target, const float *w, MlpWork ws, float *grad, float *loss, hipStream_t s);
+void adam_device(float *params, const float *grad, float *m, float *v, int n, float lr, float b1, float b2, float eps,
+                 int step, hipStream_t s);
 
 }  // namespace bh

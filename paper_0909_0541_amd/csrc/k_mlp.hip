@@ -1,0 +1,323 @@
+// Per-group opening angle chosen by a small network (12 -> 64 -> 64 -> 1).
+//
+// The paper uses one theta for every particle and studies how it trades
+// accuracy for work (Sec. 4).  Here each group gets its own theta from 12
+// features that describe how it sits in the surrounding mass:
+//   f0 = log2 c, f1 = log2(1 + R/eps), f2 = |x_g - c_g| / (R + eps),
+//   f3 = log2(l(A1) / (R + eps)), f4..7 = log2(m(Ak) / m_g),
+//   f8..11 = |com(Ak) - c_g| / l(Ak)
+// (c members, c_g box centre, R box half-diagonal, x_g members' centre of
+// mass, A1 the smallest cell that is not a bucket and holds more than c
+// particles, A(k+1) the cell above Ak, repeated at the root); then
+//   theta = 0.3 + 0.7 sigmoid(w3 . tanh(W2 tanh(W1 x' + b1) + b2) + b3 + shift),
+// x' = (x - mu) / sigma.  Inference runs on the matrix cores in bfloat16
+// (v_mfma_f32_16x16x16_bf16, FP32 accumulation); training runs in FP32 with
+// explicit forward, backward and Adam kernels, gradients summed over the
+// batch in a fixed order.
+//
+// Parameters: one FP32 vector W1 [64][12], b1 [64], W2 [64][64], b2 [64],
+// w3 [64], b3 [1].
+#include <algorithm>
+
+#include "bh_device.h"
+
+namespace bh {
+
+namespace {
+
+constexpr int kIn = 12, kHid = 64;
+constexpr int oW1 = 0, oB1 = oW1 + kHid * kIn, oW2 = oB1 + kHid, oB2 = oW2 + kHid * kHid, oW3 = oB2 + kHid,
+              oB3 = oW3 + kHid;
+static_assert(oB3 + 1 == kMlpParams, "parameter layout");
+
+// ---- features --------------------------------------------------------------
+
+__device__ __forceinline__ double norm3(double a, double b, double c) {
+  return sqrt(__dadd_rn(__dadd_rn(__dmul_rn(a, a), __dmul_rn(b, b)), __dmul_rn(c, c)));
+}
+
+__global__ void k_group_features(FeatureArgs a) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= a.info->n_groups) return;
+  const int f = a.ginfo[3 * g], c = a.ginfo[3 * g + 1], s = a.ginfo[3 * g + 2];
+  const double eps = a.eps[s];
+  double cen[3], e[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double lo = a.gbox[6 * g + k], hi = a.gbox[6 * g + 3 + k];
+    cen[k] = __dmul_rn(__dadd_rn(lo, hi), 0.5);
+    e[k] = __dsub_rn(hi, lo);
+  }
+  const double R = norm3(e[0], e[1], e[2]) / 2.0;
+  double mg = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
+  for (int i = f; i < f + c; ++i) {
+    const double m = a.smass[i];
+    const double *x = a.spos + 3 * (int64_t)i;
+    mg = __dadd_rn(mg, m);
+    mx = __dadd_rn(mx, __dmul_rn(m, x[0]));
+    my = __dadd_rn(my, __dmul_rn(m, x[1]));
+    mz = __dadd_rn(mz, __dmul_rn(m, x[2]));
+  }
+  const double re = __dadd_rn(R, eps);
+  float out[kIn];
+  out[0] = (float)log2((double)c);
+  out[1] = (float)log2(__dadd_rn(1.0, R / eps));
+  out[2] = (float)(norm3(__dsub_rn(mx / mg, cen[0]), __dsub_rn(my / mg, cen[1]), __dsub_rn(mz / mg, cen[2])) / re);
+#pragma unroll
+  for (int k = 3; k < kIn; ++k) out[k] = 0.0f;
+  // A1: the smallest proper cell (not a bucket) holding more than c particles
+  int p = a.pparent[f];
+  for (int it = 0; p >= 0 && (a.level[p] == kKeyLevels || a.ccount[p] <= c); ++it) {
+    if (it > 2 * kKeyLevels + 2) {
+      atomicOr(&a.info->err, kErrBuild);
+      p = -1;
+      break;
+    }
+    p = a.cparent[p];
+  }
+  if (p >= 0) {
+    int anc[4];
+    anc[0] = p;
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+      const int q = a.cparent[anc[k - 1]];
+      anc[k] = (q >= 0) ? q : anc[k - 1];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const NodeRec r = a.nodes[a.cslot[anc[k]]];
+      if (k == 0) out[3] = (float)log2(r.l / re);
+      out[4 + k] = (float)log2(r.m / mg);
+      out[8 + k] = (float)(norm3(__dsub_rn(r.com[0], cen[0]), __dsub_rn(r.com[1], cen[1]),
+                                 __dsub_rn(r.com[2], cen[2])) / r.l);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kIn; ++k) a.feat[g * kIn + k] = out[k];
+}
+
+// ---- inference (bfloat16 matrix cores) --------------------------------------
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> bfloat16 bits, round to nearest even (finite inputs).
+__device__ __forceinline__ short to_bf16(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ float sigmoid_theta(float y) {
+  return kThetaMin + kThetaSpan / (1.0f + expf(-y));
+}
+
+// One wave per tile of 16 rows.  Operand layout of the 16x16x16 product
+// (wave64): lane l holds A[l % 16][4 (l / 16) + v] and B[4 (l / 16) + v][l % 16]
+// for v = 0..3, and the result D[4 (l / 16) + v][l % 16].
+__global__ __launch_bounds__(kWave) void k_mlp_infer(const float *__restrict__ P, const float *__restrict__ mu,
+                                                     const float *__restrict__ sigma, const float *__restrict__ x,
+                                                     int64_t rows_host, const DevInfo *__restrict__ info, float shift,
+                                                     float *__restrict__ theta) {
+  __shared__ short h1[16][kHid + 4];
+  const int lane = lane_id();
+  const int col = lane & 15, kb = lane >> 4;
+  const int64_t rows = rows_host >= 0 ? rows_host : (int64_t)info->n_groups;
+  const int64_t tiles = (rows + 15) / 16;
+  for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    const int64_t row = t * 16 + col;
+    bf16x4 ax;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int k = 4 * kb + v;
+      float xv = 0.0f;
+      if (k < kIn && row < rows) xv = (x[row * kIn + k] - mu[k]) / sigma[k];
+      ax[v] = (k < kIn) ? to_bf16(xv) : (short)0;
+    }
+    // layer 1: 4 column blocks of 16 hidden units
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      const int j = 16 * nb + col;
+      bf16x4 bw;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = 4 * kb + v;
+        bw[v] = (k < kIn) ? to_bf16(P[oW1 + j * kIn + k]) : (short)0;
+      }
+      f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+      z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ax, bw, z, 0, 0, 0);
+      const float b = P[oB1 + j];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) h1[4 * kb + v][j] = to_bf16(tanhf(z[v] + b));
+    }
+    __syncthreads();
+    // layer 2 and the output layer
+    float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+      const int j = 16 * nb + col;
+      f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        bf16x4 ah, bw;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int k = 16 * ks + 4 * kb + v;
+          ah[v] = h1[col][k];
+          bw[v] = to_bf16(P[oW2 + j * kHid + k]);
+        }
+        z = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bw, z, 0, 0, 0);
+      }
+      const float b = P[oB2 + j], w = P[oW3 + j];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) part[v] += w * tanhf(z[v] + b);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+#pragma unroll
+      for (int d = 1; d < 16; d <<= 1) part[v] += __shfl_xor(part[v], d, kWave);
+    }
+    if (col == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = t * 16 + 4 * kb + v;
+        if (r < rows) theta[r] = sigmoid_theta(part[v] + P[oB3] + shift);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---- training (FP32) ----------------------------------------------------------
+
+// Sum of the sample weights (one block, fixed order).
+__global__ void k_weight_sum(const float *__restrict__ w, int B, float *__restrict__ out) {
+  __shared__ float s[256];
+  float acc = 0.0f;
+  for (int b = threadIdx.x; b < B; b += blockDim.x) acc += w[b];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = s[0];
+}
+
+// Forward and backward through the activations, one thread per sample.
+__global__ void k_mlp_fwd_bwd(const float *__restrict__ P, const float *__restrict__ mu,
+                              const float *__restrict__ sigma, const float *__restrict__ x,
+                              const float *__restrict__ target, const float *__restrict__ w,
+                              const float *__restrict__ wsum, int B, MlpWork ws) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  float xn[kIn], h1[kHid], h2[kHid];
+#pragma unroll
+  for (int k = 0; k < kIn; ++k) {
+    xn[k] = (x[(int64_t)b * kIn + k] - mu[k]) / sigma[k];
+    ws.xn[(int64_t)b * kIn + k] = xn[k];
+  }
+  for (int j = 0; j < kHid; ++j) {
+    float z = P[oB1 + j];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) z += P[oW1 + j * kIn + k] * xn[k];
+    h1[j] = tanhf(z);
+    ws.h1[(int64_t)b * kHid + j] = h1[j];
+  }
+  float y = P[oB3];
+  for (int j = 0; j < kHid; ++j) {
+    float z = P[oB2 + j];
+    for (int k = 0; k < kHid; ++k) z += P[oW2 + j * kHid + k] * h1[k];
+    h2[j] = tanhf(z);
+    ws.h2[(int64_t)b * kHid + j] = h2[j];
+    y += P[oW3 + j] * h2[j];
+  }
+  const float sg = 1.0f / (1.0f + expf(-y));
+  const float th = kThetaMin + kThetaSpan * sg;
+  const float W = *wsum;
+  const float r = th - target[b];
+  ws.loss[b] = w[b] * r * r / W;
+  const float dy = (2.0f * w[b] * r / W) * kThetaSpan * sg * (1.0f - sg);
+  ws.dy[b] = dy;
+  float dz2[kHid];
+  for (int j = 0; j < kHid; ++j) {
+    dz2[j] = dy * P[oW3 + j] * (1.0f - h2[j] * h2[j]);
+    ws.dz2[(int64_t)b * kHid + j] = dz2[j];
+  }
+  for (int k = 0; k < kHid; ++k) {
+    float s = 0.0f;
+    for (int j = 0; j < kHid; ++j) s += dz2[j] * P[oW2 + j * kHid + k];
+    ws.dz1[(int64_t)b * kHid + k] = s * (1.0f - h1[k] * h1[k]);
+  }
+}
+
+// Gradient of one parameter per thread: a sum over the batch in sample order.
+__global__ void k_mlp_grad(int B, MlpWork ws, float *__restrict__ grad, float *__restrict__ loss) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > kMlpParams) return;
+  float s = 0.0f;
+  if (p == kMlpParams) {
+    for (int b = 0; b < B; ++b) s += ws.loss[b];
+    if (loss) *loss = s;
+    return;
+  }
+  if (p < oB1) {
+    const int j = p / kIn, k = p % kIn;
+    for (int b = 0; b < B; ++b) s += ws.dz1[(int64_t)b * kHid + j] * ws.xn[(int64_t)b * kIn + k];
+  } else if (p < oW2) {
+    const int j = p - oB1;
+    for (int b = 0; b < B; ++b) s += ws.dz1[(int64_t)b * kHid + j];
+  } else if (p < oB2) {
+    const int j = (p - oW2) / kHid, k = (p - oW2) % kHid;
+    for (int b = 0; b < B; ++b) s += ws.dz2[(int64_t)b * kHid + j] * ws.h1[(int64_t)b * kHid + k];
+  } else if (p < oW3) {
+    const int j = p - oB2;
+    for (int b = 0; b < B; ++b) s += ws.dz2[(int64_t)b * kHid + j];
+  } else if (p < oB3) {
+    const int j = p - oW3;
+    for (int b = 0; b < B; ++b) s += ws.dy[b] * ws.h2[(int64_t)b * kHid + j];
+  } else {
+    for (int b = 0; b < B; ++b) s += ws.dy[b];
+  }
+  grad[p] = s;
+}
+
+__global__ void k_adam(float *__restrict__ P, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, int n, float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  P[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+}  // namespace
+
+void group_features_device(const FeatureArgs &a, int64_t cap, hipStream_t s) {
+  if (cap > 0) k_group_features<<<(unsigned)((cap + 127) / 128), 128, 0, s>>>(a);
+}
+
+void mlp_infer_device(const float *params, const float *mu, const float *sigma, const float *x, int64_t rows,
+                      int64_t cap_rows, const DevInfo *info, float shift, float *theta, hipStream_t s) {
+  const int64_t tiles = (cap_rows + 15) / 16;
+  if (tiles <= 0) return;
+  const unsigned grid = (unsigned)std::min<int64_t>(tiles, 4096);
+  k_mlp_infer<<<grid, kWave, 0, s>>>(params, mu, sigma, x, rows, info, shift, theta);
+}
+
+void mlp_grad_device(const float *params, const float *mu, const float *sigma, int B, const float *x,
+                     const float *target, const float *w, MlpWork ws, float *grad, float *loss, hipStream_t s) {
+  k_weight_sum<<<1, 256, 0, s>>>(w, B, ws.wsum);
+  k_mlp_fwd_bwd<<<(unsigned)((B + 63) / 64), 64, 0, s>>>(params, mu, sigma, x, target, w, ws.wsum, B, ws);
+  k_mlp_grad<<<(unsigned)((kMlpParams + 1 + 255) / 256), 256, 0, s>>>(B, ws, grad, loss);
+}
+
+void adam_device(float *params, const float *grad, float *m, float *v, int n, float lr, float b1, float b2, float eps,
+                 int step, hipStream_t s) {
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  k_adam<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(params, grad, m, v, n, lr, b1, b2, eps, c1, c2);
+}
+
+}  // namespace bh

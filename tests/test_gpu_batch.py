@@ -1,0 +1,118 @@
+"""Batched trees: many independent systems of uneven size in one set of launches.
+
+Each system of a batch must give exactly (bit for bit) what it gives when run
+alone, and match the FP64 oracle run on that system alone to the parity bar.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import check_forces, to_dev
+from paper_0909_0541_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_batch(seed=7):
+    rng = np.random.default_rng(seed)
+    sizes = [0, 1, 2, 65, 300, 1000, 4097, 2500, 0, 7000, 3, 1500]
+    pos, mass, eps, theta = [], [], [], []
+    for k, n in enumerate(sizes):
+        if k % 2 == 0:
+            p, m, _ = inputs.plummer(max(n, 1), 2000 + k, with_vel=False)
+        else:
+            p, m, _ = inputs.clustered(max(n, 1), 2000 + k, n_halos=max(1, n // 500))
+        pos.append(p[:n])
+        mass.append(m[:n] * rng.uniform(0.5, 2.0))
+        eps.append(float(np.power(max(n, 1), -1.0 / 3.0) / 20.0))
+        theta.append(float(rng.choice([0.0, 0.4, 0.6, 0.75, 1.0])))
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    return np.concatenate(pos), np.concatenate(mass), off, np.array(eps), np.array(theta)
+
+
+def _standalone(bh, p, m, eps, theta, n_crit):
+    c = bh.Context()
+    c.build_tree(to_dev(p), to_dev(m))
+    c.make_groups(n_crit)
+    a, u = c.compute_forces(eps, theta)
+    return a.cpu().numpy(), u.cpu().numpy()
+
+
+@pytest.mark.parametrize("n_crit", [16, 64])
+def test_batch_equals_standalone_and_oracle(gpu, n_crit):
+    bh = gpu
+    pos, mass, off, eps, theta = _small_batch()
+    c = bh.Context()
+    c.build_batch(off, to_dev(pos), to_dev(mass))
+    G = c.make_groups(n_crit)
+    acc, pot = c.compute_forces_batch(eps, theta)
+    acc, pot = acc.cpu().numpy(), pot.cpu().numpy()
+    st = c.get_stats()
+    assert st.error_flags == 0 and st.n_systems == len(off) - 1
+    groups = 0
+    inter = 0
+    for k in range(len(off) - 1):
+        a, b = int(off[k]), int(off[k + 1])
+        print(f"system {k}: n={b - a} eps={eps[k]:.3e} theta={theta[k]}", flush=True)
+        if b == a:
+            continue
+        sa, sp = _standalone(bh, pos[a:b], mass[a:b], eps[k], theta[k], n_crit)
+        assert np.array_equal(acc[a:b], sa), f"system {k}: batched acc differs from its standalone run"
+        assert np.array_equal(pot[a:b], sp), f"system {k}: batched pot differs from its standalone run"
+        t = oracle.Tree(pos[a:b], mass[a:b])
+        groups += t.groups(n_crit)
+        ref = t.forces(eps[k], theta[k])
+        inter += int(ref["interactions"])
+        check_forces(acc[a:b].astype(np.float64), pot[a:b].astype(np.float64), ref)
+    assert G == groups
+    assert st.interactions == inter
+
+
+def test_batch_workload_sampled_against_standalone(gpu):
+    """The 64-system batch at full size (about 3 million particles): a seeded
+    sample of systems is compared bit for bit with standalone runs, the
+    smallest system in full against the oracle."""
+    bh = gpu
+    pos, mass, off, eps = inputs.batch_systems()
+    theta = np.full(len(eps), 0.7)
+    n_crit = 64
+    c = bh.Context()
+    c.build_batch(off, to_dev(pos), to_dev(mass))
+    c.make_groups(n_crit)
+    acc, pot = c.compute_forces_batch(eps, theta)
+    acc, pot = acc.cpu().numpy(), pot.cpu().numpy()
+    assert c.get_stats().error_flags == 0
+    sizes = np.diff(off)
+    pick = set(np.random.default_rng(11).choice(len(sizes), 6, replace=False).tolist())
+    pick |= {int(np.argmin(sizes)), int(np.argmax(sizes))}
+    for k in sorted(pick):
+        a, b = int(off[k]), int(off[k + 1])
+        print(f"system {k}: n={b - a}", flush=True)
+        sa, sp = _standalone(bh, pos[a:b], mass[a:b], eps[k], theta[k], n_crit)
+        assert np.array_equal(acc[a:b], sa) and np.array_equal(pot[a:b], sp), f"system {k} differs"
+    k = int(np.argmin(sizes))
+    a, b = int(off[k]), int(off[k + 1])
+    ref = oracle.Tree(pos[a:b], mass[a:b])
+    ref.groups(n_crit)
+    check_forces(acc[a:b].astype(np.float64), pot[a:b].astype(np.float64), ref.forces(eps[k], theta[k]))
+
+
+def test_batch_argument_errors(gpu):
+    bh = gpu
+    c = bh.Context()
+    p = to_dev(np.zeros((4, 3)))
+    m = to_dev(np.ones(4))
+    with pytest.raises(bh.BHError):
+        c.build_batch([1, 4], p, m)  # offsets[0] must be 0
+    with pytest.raises(bh.BHError):
+        c.build_batch([0, 3, 2, 4], p, m)  # decreasing
+    c.build_batch([0, 2, 4], p, m)
+    c.make_groups(8)
+    with pytest.raises(ValueError):
+        c.compute_forces_batch([0.1], [0.5])  # one value per system
+    with pytest.raises(bh.BHError):
+        c.compute_forces_batch([0.1, -1.0], [0.5, 0.5])  # eps must be positive
+    with pytest.raises(bh.BHError):
+        c.compute_forces_batch([0.1, 0.1], [0.5, 1.5])  # theta above 1

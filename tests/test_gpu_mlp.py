@@ -1,0 +1,170 @@
+"""Learned per-group theta on the GPU against the FP64 oracle: features,
+bfloat16 matrix-core inference, FP32 gradients and Adam, and forces with the
+learned theta."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import check_forces, to_dev
+from oracle import mlp
+from oracle.features import group_features
+from paper_0909_0541_amd import inputs
+from test_oracle_features import _cluster
+
+pytestmark = pytest.mark.gpu
+
+
+def _f32(a):
+    return to_dev(np.asarray(a, dtype=np.float32), torch.float32)
+
+
+def _net(seed):
+    p = mlp.init(seed) + np.random.default_rng(seed + 1).normal(size=mlp.N_PARAMS) * 0.05
+    rng = np.random.default_rng(seed + 2)
+    mu = rng.normal(size=12).astype(np.float32)
+    sigma = rng.uniform(0.5, 3.0, 12).astype(np.float32)
+    return p.astype(np.float32).astype(np.float64), mu, sigma
+
+
+def _feature_cases():
+    rng = np.random.default_rng(1)
+    two = np.concatenate([_cluster([0, 0, 0], rng), _cluster([1, 1, 1], rng)])
+    nested = np.concatenate([_cluster([0.02, 0.02, 0.02], rng), _cluster([0.095, 0.02, 0.02], rng),
+                             _cluster([0.98, 0.98, 0.98], rng), _cluster([0.905, 0.98, 0.98], rng)])
+    coinc = np.concatenate([np.zeros((6, 3)), np.ones((2, 3))])
+    p8, m8, _ = inputs.plummer(8192, 1, with_vel=False)
+    pc, mc = inputs.clustered(20000, 9, n_halos=40)[:2]
+    return [("two_clusters", two, rng.uniform(0.5, 1.5, 8), 4, 1e-3),
+            ("nested", nested, rng.uniform(0.5, 1.5, 16), 4, 1e-4),
+            ("coincident", coinc, np.ones(8), 4, 0.1),
+            ("plummer_8k", p8, m8, 64, 1 / 256),
+            ("clustered_20k", pc, mc, 64, 1e-4),
+            ("whole_system", p8[:50], m8[:50], 64, 1e-2)]
+
+
+@pytest.mark.parametrize("case", _feature_cases(), ids=lambda c: c[0])
+def test_features_match_oracle(gpu, case):
+    bh = gpu
+    name, pos, mass, n_crit, eps = case
+    c = bh.Context()
+    c.build_tree(to_dev(pos), to_dev(mass))
+    G = c.make_groups(n_crit)
+    f_gpu = c.group_features(eps, G).cpu().numpy().astype(np.float64)
+    t = oracle.Tree(pos, mass)
+    assert t.groups(n_crit) == G
+    f_orc = group_features(t, eps)
+    # FP64 on both sides, one FP32 rounding on the GPU (relative 2^-24)
+    err = np.abs(f_gpu - f_orc)
+    assert np.all(err <= 1e-6 * np.maximum(1.0, np.abs(f_orc))), (name, err.max())
+
+
+@pytest.mark.parametrize("rows", [0, 1, 17, 1003, 4096])
+def test_inference_matches_bf16_oracle(gpu, rows):
+    bh = gpu
+    p, mu, sigma = _net(3)
+    x = np.random.default_rng(rows).normal(size=(rows, 12)).astype(np.float32) * 3.0
+    c = bh.Context()
+    th = c.mlp_infer(_f32(p), _f32(mu), _f32(sigma), _f32(x.reshape(rows, 12)), shift=0.25)
+    th = th.cpu().numpy().astype(np.float64)
+    if rows == 0:
+        return
+    ref = mlp.forward_bf16(p, x, mu, sigma, 0.25)
+    # Same bfloat16 operands on both sides; the sums differ in FP32 rounding
+    # order (relative ~1e-6), which can flip the bfloat16 rounding of a first-
+    # layer activation (a step of 2^-8 relative) now and then.  One flip moves
+    # theta by at most 0.7/4 * |w3|max * |W2|max * 2^-8.
+    one_flip = 0.7 / 4 * np.abs(mlp.unpack(p)["w3"]).max() * np.abs(mlp.unpack(p)["W2"]).max() * 2.0 ** -8
+    err = np.abs(th - ref)
+    assert np.quantile(err, 0.99) <= 1e-5, np.quantile(err, 0.99)
+    assert err.max() <= 4 * one_flip + 1e-5, (err.max(), one_flip)
+    # and it is the network of the FP64 definition up to bfloat16 precision
+    full, _ = mlp.forward(p, x, mu, sigma, 0.25)
+    assert np.abs(th - full).max() < 0.02
+
+
+@pytest.mark.parametrize("batch", [1, 333, 2048])
+def test_gradient_matches_oracle(gpu, batch):
+    bh = gpu
+    p, mu, sigma = _net(5)
+    rng = np.random.default_rng(batch)
+    x = (rng.normal(size=(batch, 12)) * 2.0).astype(np.float32)
+    t = rng.uniform(0.3, 1.0, batch).astype(np.float32)
+    w = rng.uniform(0.5, 50.0, batch).astype(np.float32)
+    c = bh.Context()
+    g, loss = c.mlp_grad(_f32(p), _f32(mu), _f32(sigma), _f32(x), _f32(t), _f32(w))
+    g = g.cpu().numpy().astype(np.float64)
+    loss = float(loss.cpu().numpy()[0])
+    l_ref, g_ref = mlp.loss_and_grad(p, x.astype(np.float64), mu.astype(np.float64), sigma.astype(np.float64),
+                                     t.astype(np.float64), w.astype(np.float64))
+    assert abs(loss - l_ref) <= 1e-5 * l_ref
+    assert np.linalg.norm(g - g_ref) <= 1e-4 * np.linalg.norm(g_ref)
+    assert np.abs(g - g_ref).max() <= 1e-4 * np.abs(g_ref).max()
+
+
+def test_adam_matches_oracle(gpu):
+    bh = gpu
+    n = mlp.N_PARAMS
+    rng = np.random.default_rng(7)
+    p0 = rng.normal(size=n).astype(np.float32)
+    c = bh.Context()
+    P, M, V = _f32(p0), torch.zeros(n, dtype=torch.float32, device="cuda"), torch.zeros(n, dtype=torch.float32,
+                                                                                          device="cuda")
+    opt = mlp.Adam(n, lr=1e-2)
+    pr = p0.astype(np.float64)
+    for step in range(1, 4):
+        g = rng.normal(size=n).astype(np.float32)
+        c.mlp_adam(P, _f32(g), M, V, step, 1e-2)
+        pr = opt.step(pr, g.astype(np.float64))
+    assert np.abs(P.cpu().numpy() - pr).max() <= 1e-6 * max(1.0, np.abs(pr).max())
+
+
+def test_training_on_gpu_fits_a_learnable_target(gpu):
+    bh = gpu
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=(512, 12))
+    t = 0.3 + 0.7 / (1.0 + np.exp(-(1.5 * x[:, 0] - x[:, 1])))
+    mu, sigma = x.mean(axis=0), x.std(axis=0)
+    p = mlp.init(6)
+    c = bh.Context()
+    P = _f32(p)
+    M = torch.zeros_like(P)
+    V = torch.zeros_like(P)
+    X, T, W, MU, SG = _f32(x), _f32(t), _f32(np.ones(512)), _f32(mu), _f32(sigma)
+    _, l0 = c.mlp_grad(P, MU, SG, X, T, W)
+    l0 = float(l0.cpu()[0])
+    for step in range(1, 301):
+        g, _ = c.mlp_grad(P, MU, SG, X, T, W)
+        c.mlp_adam(P, g, M, V, step, 3e-3)
+    _, l1 = c.mlp_grad(P, MU, SG, X, T, W)
+    assert float(l1.cpu()[0]) < 0.05 * l0
+    # the FP64 oracle trained the same way ends at a comparable loss
+    opt = mlp.Adam(mlp.N_PARAMS, lr=3e-3)
+    for _ in range(300):
+        _, gr = mlp.loss_and_grad(p, x, mu, sigma, t, np.ones(512))
+        p = opt.step(p, gr)
+    l_ref, _ = mlp.loss_and_grad(p, x, mu, sigma, t, np.ones(512))
+    assert float(l1.cpu()[0]) < 3.0 * l_ref + 1e-6
+
+
+def test_group_theta_and_forces_with_learned_theta(gpu):
+    bh = gpu
+    pos, mass = inputs.clustered(20000, 12, n_halos=40)[:2]
+    eps, n_crit = 1e-4, 64
+    p, mu, sigma = _net(11)
+    c = bh.Context()
+    c.build_tree(to_dev(pos), to_dev(mass))
+    G = c.make_groups(n_crit)
+    P, MU, SG = _f32(p), _f32(mu), _f32(sigma)
+    th = c.group_theta(P, MU, SG, eps, shift=-0.3)
+    feat = c.group_features(eps, G)
+    th2 = c.mlp_infer(P, MU, SG, feat.contiguous(), shift=-0.3)
+    assert torch.equal(th[:G], th2)
+    thv = th[:G].cpu().numpy().astype(np.float64)
+    assert np.all((thv >= 0.3) & (thv <= 1.0)) and thv.std() > 0.01
+    acc, pot = c.compute_forces(eps, 0.6, theta_group=th[:G].contiguous())
+    assert c.get_stats().error_flags == 0
+    t = oracle.Tree(pos, mass)
+    t.groups(n_crit)
+    ref = t.forces(eps, 0.6, theta_g=thv)
+    check_forces(acc.cpu().numpy().astype(np.float64), pot.cpu().numpy().astype(np.float64), ref)
