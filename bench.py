@@ -3,15 +3,18 @@
 
 One step = the whole hot path over one synthetic particle set already
 resident in HBM: root cube, Morton keys, radix sort, tree topology and
-moments, groups, and the fused group walk + FP32 force sum.  Default
-workload: clustered box, N = 2,097,152 (30% uniform + 70% in 512 Plummer
-halos), eps = 1e-4, theta = 0.6, n_crit = 256.
+moments, groups, the group walk writing the interaction lists, and the FP32
+force sum.  Default workload: clustered box, N = 2,097,152 (30% uniform + 70%
+in 512 Plummer halos), eps = 1e-4, n_crit = 256.
 
+Before timing, theta is bisected until the RMS relative force error against
+FP64 direct summation on a seeded sample of 4096 particles is 1e-3 (+-3%).
 Prints one JSON line.  value = tree-force interactions per second of whole
-steps (sum over members of list length - 1, divided by the step time);
-particles/s, the RMS force error against FP64 direct summation on a seeded
-sample, the roofline of the dominant kernel (the force sum, FP32 VALU) and
-the FP64 CPU oracle's throughput on a bounded sample are reported beside it.
+steps at that theta (sum over members of list length - 1, divided by the
+step time).  Beside it: particles/s; the learned per-group theta at the same
+error (its output shift bisected the same way, features + network in the
+step); the workload's own theta of 0.6; the roofline of the dominant kernel
+(the force sum, FP32 VALU); and the FP64 CPU oracle's throughput.
 """
 from __future__ import annotations
 
@@ -64,6 +67,9 @@ def parse():
     ap.add_argument("--target-rms", type=float, default=1e-3,
                     help="calibrate theta by bisection to this RMS force error before timing "
                          "(0: time the workload's own theta)")
+    ap.add_argument("--theta-net", default=os.path.join(ROOT, "paper_0909_0541_amd", "theta_net.npz"),
+                    help="trained per-group theta network (the learned leg is skipped when missing)")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--copy-check-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the timed steps, "
                          "as the reference kernel that scales HBM byte counters")
@@ -121,32 +127,6 @@ def _cpu_model():
     return "unknown"
 
 
-def bisect_theta(rms_of, target, lo=0.3, hi=1.0, rel_tol=0.03, iters=14):
-    """theta in [lo, hi] whose RMS force error is within rel_tol of target
-    (the error grows with theta); returns (theta, rms) of the closest try."""
-    best = None
-    r_lo, r_hi = rms_of(lo), rms_of(hi)
-    for th, r in ((lo, r_lo), (hi, r_hi)):
-        if best is None or abs(r / target - 1) < abs(best[1] / target - 1):
-            best = (th, r)
-    if r_hi <= target:
-        return hi, r_hi
-    if r_lo >= target:
-        return lo, r_lo
-    for _ in range(iters):
-        mid = 0.5 * (lo + hi)
-        r = rms_of(mid)
-        if abs(r / target - 1) < abs(best[1] / target - 1):
-            best = (mid, r)
-        if abs(r / target - 1) <= rel_tol:
-            break
-        if r > target:
-            hi = mid
-        else:
-            lo = mid
-    return best
-
-
 def main():
     args = parse()
     if args.gpus != 1:
@@ -156,44 +136,24 @@ def main():
     import numpy as np
     import torch
 
-    from paper_0909_0541_amd import bh, inputs
+    from paper_0909_0541_amd import bh, inputs, learned
 
     torch.cuda.set_device(0)
     pos, mass, _, w = inputs.make_workload(args.workload, n=args.n)
     n = pos.shape[0]
     dpos = torch.as_tensor(pos, device="cuda")
     dmass = torch.as_tensor(mass, device="cuda")
-    acc = torch.empty((n, 3), dtype=torch.float32, device="cuda")
-    pot = torch.empty(n, dtype=torch.float32, device="cuda")
     ctx = bh.Context(timing=True, waves_per_cu=args.waves_per_cu)
-
-    def step(theta):
-        ctx.build_tree(dpos, dmass)
-        ctx.make_groups(w.n_crit, sync=False)
-        ctx.compute_forces(w.eps, theta, acc=acc, pot=pot)
-
-    # judge: FP64 direct summation on the GPU for a seeded sample
-    rng = np.random.default_rng(12345)
-    s = min(args.judge_sample, n)
-    idx = np.sort(rng.choice(n, s, replace=False))
-    didx = torch.as_tensor(idx, device="cuda")
-    a_dir, _ = ctx.direct_sampled(dpos, dmass, w.eps, didx)
-    a_dir = a_dir.cpu().numpy()
-    a_dir_norm = np.linalg.norm(a_dir, axis=1)
-
-    def rms_now():
-        a_tree = acc[didx].double().cpu().numpy()
-        rel = np.linalg.norm(a_tree - a_dir, axis=1) / a_dir_norm
-        return float(math.sqrt(np.mean(rel * rel)))
-
-    def rms_of(theta):
-        step(theta)
-        return rms_now()
+    judge = learned.Judge(ctx, dpos, dmass, w.eps, args.judge_sample)
+    fixed = learned.Stepper(ctx, dpos, dmass, w.eps, w.n_crit)
 
     calib = None
     theta = w.theta
     if args.target_rms > 0:
-        theta, r = bisect_theta(rms_of, args.target_rms)
+        def rms_of(th):
+            fixed(theta=th)
+            return judge.rms(fixed.acc)
+        theta, r = learned.bisect(rms_of, 0.3, 1.0, args.target_rms)
         calib = {"target_rms": args.target_rms, "theta": theta, "rms": r, "band": 0.03,
                  "search": "bisection over theta in [0.3, 1.0]"}
 
@@ -206,29 +166,14 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    def timed(theta_run):
-        for _ in range(args.warmup):
-            step(theta_run)
-        torch.cuda.synchronize()
-        ctx.get_stats()  # clears the warm-up timings
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(args.steps):
-            step(theta_run)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.steps
-        st = ctx.get_stats()
-        if st.error_flags:
-            raise SystemExit(f"device error flags {st.error_flags}")
+    def stages(st):
         per = lambda t, k: t / max(k, 1)
-        return ms, st, {"build": per(st.t_build_ms, st.n_build_calls), "groups": per(st.t_groups_ms, st.n_groups_calls),
-                        "walk": per(st.t_walk_ms, st.n_walk_calls), "force": per(st.t_force_ms, st.n_force_calls)}
+        return {"build": per(st.t_build_ms, st.n_build_calls), "groups": per(st.t_groups_ms, st.n_groups_calls),
+                "walk": per(st.t_walk_ms, st.n_walk_calls), "force": per(st.t_force_ms, st.n_force_calls)}
 
-    ms_per_step, st, stage = timed(theta)
-    rms = rms_now()
+    ms_per_step, st = learned.timed_steps(fixed, args.steps, args.warmup, theta=theta)
+    stage = stages(st)
+    rms = judge.rms(fixed.acc)
     inter = st.interactions
     value = inter / (ms_per_step * 1e-3)
     t_force = stage["force"]
@@ -253,7 +198,7 @@ def main():
         "interactions_per_step": inter,
         "interactions_per_particle": inter / n,
         "rms_force_error": rms,
-        "judge_sample": s,
+        "judge_sample": int(judge.idx.shape[0]),
         "theta_calibration": calib,
         "groups": st.n_groups,
         "cells": st.n_cells,
@@ -265,13 +210,34 @@ def main():
         "force_kernel_interactions_per_s": inter / (t_force * 1e-3),
         "walk_plus_force_interactions_per_s": inter / ((stage["walk"] + t_force) * 1e-3),
     }
+    if calib is not None and not args.no_learned and os.path.exists(args.theta_net):
+        net = learned.ThetaNet.load(args.theta_net)
+        lstep = learned.Stepper(ctx, dpos, dmass, w.eps, w.n_crit, net)
+
+        def rms_shift(sh):
+            lstep(shift=sh)
+            return judge.rms(lstep.acc)
+        sh, r = learned.bisect(rms_shift, -8.0, 8.0, args.target_rms)
+        if abs(r / args.target_rms - 1) <= 0.03 or r <= args.target_rms:
+            ms_l, st_l = learned.timed_steps(lstep, args.steps, args.warmup, shift=sh)
+            tg = lstep.theta_g[:st_l.n_groups].cpu().numpy()
+            line["learned"] = {
+                "shift": sh, "rms_force_error": judge.rms(lstep.acc), "ms_per_step": ms_l,
+                "interactions_per_step": st_l.interactions, "interactions_per_s": st_l.interactions / (ms_l * 1e-3),
+                "particles_per_s": n / (ms_l * 1e-3), "stage_ms": stages(st_l),
+                "theta_mean": float(tg.mean()), "theta_min": float(tg.min()), "theta_max": float(tg.max()),
+                "interactions_saved": 1.0 - st_l.interactions / inter,
+                "particles_per_s_vs_fixed": (n / (ms_l * 1e-3)) / line["particles_per_s"]}
+        else:
+            line["learned"] = {"fallback_to_fixed": True, "shift": sh, "rms_force_error": r}
     if calib is not None and abs(theta - w.theta) > 1e-12:
-        ms2, st2, stage2 = timed(w.theta)
+        ms2, st2 = learned.timed_steps(fixed, args.steps, args.warmup, theta=w.theta)
+        s2 = stages(st2)
         line["at_workload_theta"] = {
-            "theta": w.theta, "rms_force_error": rms_now(), "ms_per_step": ms2,
+            "theta": w.theta, "rms_force_error": judge.rms(fixed.acc), "ms_per_step": ms2,
             "interactions_per_s": st2.interactions / (ms2 * 1e-3), "particles_per_s": n / (ms2 * 1e-3),
-            "interactions_per_step": st2.interactions, "stage_ms": stage2,
-            "force_kernel_tflops": FLOPS_PER_INTERACTION * st2.interactions / (stage2["force"] * 1e-3) / 1e12}
+            "interactions_per_step": st2.interactions, "stage_ms": s2,
+            "force_kernel_tflops": FLOPS_PER_INTERACTION * st2.interactions / (s2["force"] * 1e-3) / 1e12}
     if not args.no_cpu_baseline:
         w_cpu = w if calib is None else dataclasses.replace(w, theta=theta)
         line["cpu_baseline"] = cpu_baseline(pos, mass, w_cpu, inter, args.cpu_seconds)

@@ -215,14 +215,21 @@ bh_status bh_energy(bh_ctx *ctx, int64_t n, const double *vel, const double *mas
 /* The paper fixes one opening angle and studies its accuracy/work trade-off
  * (Sec. 4).  These calls let a small network choose theta per group instead:
  * 12 group features -> tanh(64) -> tanh(64) -> theta = 0.3 + 0.7 sigmoid(y +
- * shift).  Features (FP32, per group, from the current tree and groups):
+ * shift).  Features (FP32, per group, from the current tree and groups; c the
+ * member count, c_g the box centre, R the box half-diagonal, x_g and m_g the
+ * members' centre of mass and mass, A1 the smallest cell (not a bucket of
+ * equal keys) holding more than c particles, A2 the cell above it (A1 at the
+ * root)):
  *   f0 = log2 c, f1 = log2(1 + R/eps), f2 = |x_g - c_g| / (R + eps),
- *   f3 = log2(l(A1) / (R + eps)), f4..f7 = log2(m(Ak) / m_g),
- *   f8..f11 = |com(Ak) - c_g| / l(Ak), k = 1..4,
- * with c the member count, c_g the box centre, R the box half-diagonal, x_g
- * and m_g the members' centre of mass and mass, A1 the smallest cell (not a
- * bucket of equal keys) holding more than c particles, A(k+1) the cell above
- * Ak (Ak again at the root); a group that is a whole system has f3..f11 = 0. */
+ *   f3 = log2(l(A1) / (R + eps)), f4 = log2(m(A1) / m_g),
+ *   f5 = |com(A1) - c_g| / l(A1), f11 = log2(m(A2) / m_g)
+ * (f3, f4, f5, f11 = 0 for a group that is a whole system), and from the
+ * group's interaction list at theta = 1, with d = com - c_g over the entries
+ * whose centre of mass lies outside the box:
+ *   f6 = log2(|sum m d / (|d|^2 + eps^2)^(3/2)| + 2^-100),
+ *   f7 = log2(sum m / (|d|^2 + eps^2) + 2^-100),
+ *   f8 = log2(1 + single-particle entries outside the box),
+ *   f9 = log2(list length), f10 = log2(mass of the entries inside the box / m_g). */
 #define BH_MLP_FEATURES 12
 #define BH_MLP_HIDDEN 64
 #define BH_MLP_PARAMS 5057

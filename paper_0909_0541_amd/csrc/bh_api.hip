@@ -709,6 +709,17 @@ static bh_status features_common(bh_ctx *c, const double *eps_sys, float *feat) 
   a.info = P<DevInfo>(c->info);
   a.feat = feat;
   group_features_device(a, c->n, c->stream);
+  ProbeArgs pa{};
+  pa.nodes = P<NodeRec>(c->nodes);
+  pa.ginfo = P<int32_t>(c->ginfo);
+  pa.gbox = P<double>(c->gbox);
+  pa.smass = P<double>(c->smass);
+  pa.eps = P<double>(c->feps);
+  pa.info = P<DevInfo>(c->info);
+  pa.nsys = c->nsys;
+  pa.feat = feat;
+  if (c->probe_bpc == 0) c->probe_bpc = probe_blocks_per_cu();
+  probe_device(pa, c->num_cu * c->probe_bpc, c->stream);
   return hip_check(c, hipGetLastError(), "kernel launch (features)");
 }
 

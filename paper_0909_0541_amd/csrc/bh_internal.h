@@ -104,7 +104,7 @@ struct bh_ctx {
   int num_cu = 0;
   std::string err;
   bh_options opt{0, 0};
-  int walk_bpc = 0, force_bpc = 0;  // resident blocks per CU of the persistent kernels
+  int walk_bpc = 0, force_bpc = 0, probe_bpc = 0;  // resident blocks per CU of the persistent kernels
 
   // current tree
   int64_t n = 0;
@@ -265,6 +265,19 @@ struct WalkListArgs {
   double *gmass;
 };
 void walk_lists_device(const WalkListArgs &a, int grid, hipStream_t s);
+// probe walk at theta = 1 for the learned-theta features f6..f10
+struct ProbeArgs {
+  const NodeRec *nodes;
+  const int32_t *ginfo;
+  const double *gbox;
+  const double *smass;
+  const double *eps;  // per system
+  DevInfo *info;      // queue must be reset before the launch
+  int nsys;
+  float *feat;        // [G][12]
+};
+void probe_device(const ProbeArgs &a, int grid, hipStream_t s);
+int probe_blocks_per_cu();
 int walk_lists_blocks_per_cu();  // resident single-wave blocks per CU
 
 // k_force.hip: force sums over the lists

@@ -2,13 +2,19 @@
 //
 // The paper uses one theta for every particle and studies how it trades
 // accuracy for work (Sec. 4).  Here each group gets its own theta from 12
-// features that describe how it sits in the surrounding mass:
+// features that describe how it sits in the surrounding mass (c members,
+// c_g box centre, R box half-diagonal, x_g and m_g the members' centre of mass
+// and mass, A1 the smallest cell that is not a bucket and holds more than c
+// particles, A2 the cell above it, A1 again at the root):
 //   f0 = log2 c, f1 = log2(1 + R/eps), f2 = |x_g - c_g| / (R + eps),
-//   f3 = log2(l(A1) / (R + eps)), f4..7 = log2(m(Ak) / m_g),
-//   f8..11 = |com(Ak) - c_g| / l(Ak)
-// (c members, c_g box centre, R box half-diagonal, x_g members' centre of
-// mass, A1 the smallest cell that is not a bucket and holds more than c
-// particles, A(k+1) the cell above Ak, repeated at the root); then
+//   f3 = log2(l(A1) / (R + eps)), f4 = log2(m(A1) / m_g),
+//   f5 = |com(A1) - c_g| / l(A1), f11 = log2(m(A2) / m_g),
+// and, from the group's interaction list at theta = 1 (the probe walk) with
+// d = com - c_g over the entries outside the box:
+//   f6 = log2(|sum m d / (d^2 + eps^2)^1.5| + 2^-100),
+//   f7 = log2(sum m / (d^2 + eps^2) + 2^-100),
+//   f8 = log2(1 + single particles outside the box), f9 = log2(list length),
+//   f10 = log2(mass of the entries inside the box / m_g); then
 //   theta = 0.3 + 0.7 sigmoid(w3 . tanh(W2 tanh(W1 x' + b1) + b2) + b3 + shift),
 // x' = (x - mu) / sigma.  Inference runs on the matrix cores in bfloat16
 // (v_mfma_f32_16x16x16_bf16, FP32 accumulation); training runs in FP32 with
@@ -76,24 +82,19 @@ __global__ void k_group_features(FeatureArgs a) {
     p = a.cparent[p];
   }
   if (p >= 0) {
-    int anc[4];
-    anc[0] = p;
-#pragma unroll
-    for (int k = 1; k < 4; ++k) {
-      const int q = a.cparent[anc[k - 1]];
-      anc[k] = (q >= 0) ? q : anc[k - 1];
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const NodeRec r = a.nodes[a.cslot[anc[k]]];
-      if (k == 0) out[3] = (float)log2(r.l / re);
-      out[4 + k] = (float)log2(r.m / mg);
-      out[8 + k] = (float)(norm3(__dsub_rn(r.com[0], cen[0]), __dsub_rn(r.com[1], cen[1]),
-                                 __dsub_rn(r.com[2], cen[2])) / r.l);
-    }
+    const int q = a.cparent[p];
+    const NodeRec r1 = a.nodes[a.cslot[p]];
+    const NodeRec r2 = a.nodes[a.cslot[q >= 0 ? q : p]];
+    out[3] = (float)log2(r1.l / re);
+    out[4] = (float)log2(r1.m / mg);
+    out[5] = (float)(norm3(__dsub_rn(r1.com[0], cen[0]), __dsub_rn(r1.com[1], cen[1]), __dsub_rn(r1.com[2], cen[2])) /
+                     r1.l);
+    out[11] = (float)log2(r2.m / mg);
   }
+  // f6..f10 come from the probe walk (k_probe), which runs after this kernel
 #pragma unroll
-  for (int k = 0; k < kIn; ++k) a.feat[g * kIn + k] = out[k];
+  for (int k = 0; k < kIn; ++k)
+    if (k < 6 || k == 11) a.feat[g * kIn + k] = out[k];
 }
 
 // ---- inference (bfloat16 matrix cores) --------------------------------------

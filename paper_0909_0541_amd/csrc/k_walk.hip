@@ -235,6 +235,148 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
   }
 }
 
+__global__ void k_reset_queue(DevInfo *info) { info->queue = 0; }
+
+// Probe walk of the learned-theta features: the group walk at theta = 1 (the
+// same opening test and traversal as k_walk_lists), summing over the entries
+// instead of writing them: the field and its scale at the box centre from the
+// entries outside the box, the count of single particles among them, the list
+// length and the mass of the entries inside the box.  Writes features f6..f10.
+__global__ __launch_bounds__(kWave) void k_probe(ProbeArgs a) {
+  __shared__ int2 stk[kStack];
+  __shared__ int mark[kWave];
+  const int lane = lane_id();
+  const int G = a.info->n_groups;
+  const int nslots = a.nsys + a.info->n_slots;
+  for (;;) {
+    const int g = take_one(&a.info->queue, lane);
+    if (g >= G) break;
+    const int gf = a.ginfo[3 * g], gc = a.ginfo[3 * g + 1], gs = a.ginfo[3 * g + 2];
+    double blo[3], bhi[3], cen[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      blo[k] = a.gbox[6 * (int64_t)g + k];
+      bhi[k] = a.gbox[6 * (int64_t)g + 3 + k];
+      cen[k] = __dmul_rn(__dadd_rn(blo[k], bhi[k]), 0.5);
+    }
+    const double eps = a.eps[gs];
+    const double eps2 = __dmul_rn(eps, eps);
+    double ax = 0.0, ay = 0.0, az = 0.0, S = 0.0, m_in = 0.0;
+    int n_part = 0, nlist = 0;
+    bool corrupt = false;
+    int sp = 1;
+    int budget = 2 * nslots + 2;
+    if (lane == 0) stk[0] = make_int2(gs, 1);
+    wave_sync();
+    while (sp > 0) {
+      if (--budget < 0) {
+        corrupt = true;
+        break;
+      }
+      const bool starved = sp > kStack - kWave - kReserve;
+      const int nread = starved ? 1 : min(sp, kWave);
+      int2 e = make_int2(0, 0);
+      if (lane < nread) e = stk[sp - 1 - lane];
+      const int cnt = (lane < nread) ? e.y : 0;
+      const int pre = wave_inclusive_sum(cnt);
+      const int total = __shfl(pre, nread - 1, kWave);
+      const int B = min(starved ? 8 : kWave, total);
+      const int start = pre - cnt;
+      const int kfull = __popcll(__ballot(lane < nread && pre <= B));
+      mark[lane] = -1;
+      wave_sync();
+      if (lane < nread && start < B) mark[start] = lane;
+      wave_sync();
+      const int ei = wave_inclusive_max(mark[lane]);
+      const int e_start = __shfl(start, ei < 0 ? 0 : ei, kWave);
+      const int e_first = __shfl(e.x, ei < 0 ? 0 : ei, kWave);
+      const int nsp = sp - kfull;
+      if (kfull < nread) {
+        const int pstart = __shfl(start, kfull, kWave);
+        if (pstart < B && lane == kfull) stk[sp - 1 - kfull] = make_int2(e.x + (B - pstart), e.y - (B - pstart));
+      }
+      const int node = e_first + (lane - e_start);
+      if (__ballot(lane < B && (node < 0 || node >= nslots))) {
+        corrupt = true;
+        break;
+      }
+      bool push = false, emit = false;
+      int2 rng = make_int2(0, 0);
+      if (lane < B) {
+        const NodeRec r = a.nodes[node];
+        double d2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const double below = __dsub_rn(blo[k], r.com[k]);
+          const double above = __dsub_rn(r.com[k], bhi[k]);
+          const double ek = fmax(0.0, fmax(below, above));
+          d2 = (k == 0) ? __dmul_rn(ek, ek) : __dadd_rn(d2, __dmul_rn(ek, ek));
+        }
+        if (r.child < 0) {
+          emit = true;
+        } else {
+          const double q = __dadd_rn(r.l, r.s);  // l / theta + s at theta = 1
+          if (d2 > __dmul_rn(q, q)) emit = true;
+          else push = true;
+        }
+        if (emit) {
+          if (d2 == 0.0) {
+            m_in = __dadd_rn(m_in, r.m);
+          } else {
+            const double dx = __dsub_rn(r.com[0], cen[0]), dy = __dsub_rn(r.com[1], cen[1]),
+                         dz = __dsub_rn(r.com[2], cen[2]);
+            const double r2 =
+                __dadd_rn(__dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz)), eps2);
+            const double w = r.m / __dmul_rn(r2, sqrt(r2));
+            ax = __dadd_rn(ax, __dmul_rn(w, dx));
+            ay = __dadd_rn(ay, __dmul_rn(w, dy));
+            az = __dadd_rn(az, __dmul_rn(w, dz));
+            S = __dadd_rn(S, r.m / r2);
+            if (r.child < 0) ++n_part;
+          }
+        }
+        if (push) rng = make_int2(r.child, r.nchild);
+      }
+      const unsigned long long pm = __ballot(push);
+      const int npush = __popcll(pm);
+      if (nsp + npush > kStack) {
+        corrupt = true;
+        break;
+      }
+      if (push) stk[nsp + rank_below(pm)] = rng;
+      nlist += __popcll(__ballot(emit));
+      wave_sync();
+      sp = nsp + npush;
+    }
+    if (corrupt) {
+      if (lane == 0) atomicOr(&a.info->err, kErrStack);
+      continue;
+    }
+    double mg = 0.0;
+    for (int i = gf + lane; i < gf + gc; i += kWave) mg = __dadd_rn(mg, a.smass[i]);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      ax += shfl_xor_d(ax, d);
+      ay += shfl_xor_d(ay, d);
+      az += shfl_xor_d(az, d);
+      S += shfl_xor_d(S, d);
+      m_in += shfl_xor_d(m_in, d);
+      mg += shfl_xor_d(mg, d);
+      n_part += __shfl_xor(n_part, d, kWave);
+    }
+    if (lane == 0) {
+      const double tiny = 0x1p-100;
+      float *f = a.feat + 12 * (int64_t)g;
+      f[6] = (float)log2(__dadd_rn(sqrt(__dadd_rn(__dadd_rn(__dmul_rn(ax, ax), __dmul_rn(ay, ay)), __dmul_rn(az, az))),
+                                   tiny));
+      f[7] = (float)log2(__dadd_rn(S, tiny));
+      f[8] = (float)log2(1.0 + (double)n_part);
+      f[9] = (float)log2((double)nlist);
+      f[10] = (float)log2(m_in / mg);
+    }
+  }
+}
+
 }  // namespace
 
 int walk_lists_blocks_per_cu() {
@@ -245,6 +387,17 @@ int walk_lists_blocks_per_cu() {
 
 void walk_lists_device(const WalkListArgs &a, int grid, hipStream_t s) {
   k_walk_lists<<<(unsigned)grid, kWave, 0, s>>>(a);
+}
+
+int probe_blocks_per_cu() {
+  int b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_probe, kWave, 0) != hipSuccess || b < 1) b = 8;
+  return b;
+}
+
+void probe_device(const ProbeArgs &a, int grid, hipStream_t s) {
+  k_reset_queue<<<1, 1, 0, s>>>(a.info);
+  k_probe<<<(unsigned)grid, kWave, 0, s>>>(a);
 }
 
 }  // namespace bh

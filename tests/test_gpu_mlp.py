@@ -8,7 +8,7 @@ import torch
 import oracle
 from gpu_helpers import check_forces, to_dev
 from oracle import mlp
-from oracle.features import group_features
+from oracle.features import all_features
 from paper_0909_0541_amd import inputs
 from test_oracle_features import _cluster
 
@@ -53,7 +53,7 @@ def test_features_match_oracle(gpu, case):
     f_gpu = c.group_features(eps, G).cpu().numpy().astype(np.float64)
     t = oracle.Tree(pos, mass)
     assert t.groups(n_crit) == G
-    f_orc = group_features(t, eps)
+    f_orc = all_features(t, eps)
     # FP64 on both sides, one FP32 rounding on the GPU (relative 2^-24)
     err = np.abs(f_gpu - f_orc)
     assert np.all(err <= 1e-6 * np.maximum(1.0, np.abs(f_orc))), (name, err.max())

@@ -2,16 +2,17 @@
 import numpy as np
 
 import oracle
-from oracle.features import group_features
+from oracle.features import TINY, all_features, group_features, probe_features
 
 
 def _cluster(c, rng, k=4, r=1e-3):
     return np.asarray(c, dtype=np.float64) + rng.uniform(-r, r, (k, 3))
 
 
-def _expected(members, all_pos, all_mass, idx, anc, side, eps):
-    """Features from the definition, with the ancestor cells given by hand
-    as (particle index set, side)."""
+def _expected(all_pos, all_mass, idx, anc, eps):
+    """f0..f5 and f11 from the definition, with the ancestor cells A_1, A_2
+    given by hand as (particle index set, side); the probe features f6..f10
+    are not part of group_features and stay 0."""
     p = all_pos[idx]
     m = all_mass[idx]
     lo, hi = p.min(axis=0), p.max(axis=0)
@@ -19,14 +20,13 @@ def _expected(members, all_pos, all_mass, idx, anc, side, eps):
     R = np.linalg.norm(hi - lo) / 2
     mg = m.sum()
     xg = (m[:, None] * p).sum(axis=0) / mg
-    f = [np.log2(len(idx)), np.log2(1 + R / eps), np.linalg.norm(xg - cen) / (R + eps),
-         np.log2(anc[0][1] / (R + eps))]
-    for s, _ in anc:
-        f.append(np.log2(all_mass[s].sum() / mg))
-    for s, l in anc:
-        com = (all_mass[s][:, None] * all_pos[s]).sum(axis=0) / all_mass[s].sum()
-        f.append(np.linalg.norm(com - cen) / l)
-    return np.array(f)
+    (s1, l1), (s2, _) = anc
+    com1 = (all_mass[s1][:, None] * all_pos[s1]).sum(axis=0) / all_mass[s1].sum()
+    f = np.zeros(12)
+    f[:6] = [np.log2(len(idx)), np.log2(1 + R / eps), np.linalg.norm(xg - cen) / (R + eps), np.log2(l1 / (R + eps)),
+             np.log2(all_mass[s1].sum() / mg), np.linalg.norm(com1 - cen) / l1]
+    f[11] = np.log2(all_mass[s2].sum() / mg)
+    return f
 
 
 def test_two_clusters_root_is_every_ancestor():
@@ -46,7 +46,7 @@ def test_two_clusters_root_is_every_ancestor():
     allidx = np.arange(8)
     for g in range(2):
         idx = perm[first[g]:first[g] + count[g]]
-        exp = _expected(None, pos, mass, np.sort(idx), [(allidx, side)] * 4, side, eps)
+        exp = _expected(pos, mass, np.sort(idx), [(allidx, side)] * 2, eps)
         assert np.allclose(f[g], exp, rtol=1e-12, atol=1e-12), (g, f[g], exp)
 
 
@@ -75,8 +75,8 @@ def test_nested_clusters_skip_single_child_cells():
         sup = sets[k]
         # the supercluster's split cell: the level-3 cube (side/8) holding both
         # of its clusters; above it only single-child cells up to the root
-        anc = [(sup, side / 8), (np.arange(16), side), (np.arange(16), side), (np.arange(16), side)]
-        exp = _expected(None, pos, mass, idx, anc, side, eps)
+        anc = [(sup, side / 8), (np.arange(16), side)]
+        exp = _expected(pos, mass, idx, anc, eps)
         assert np.allclose(f[g], exp, rtol=1e-12, atol=1e-12), (g, f[g], exp)
     assert seen == {0, 1, 2, 3}
 
@@ -90,6 +90,10 @@ def test_whole_system_group_has_no_ancestor():
     f = group_features(t, 0.01)
     assert f[0, 0] == np.log2(10)
     assert np.all(f[0, 3:] == 0.0)
+    pf = probe_features(t, 0.01)
+    # no entry lies outside the box of a whole system: no field, list = all particles
+    assert pf[0, 0] == np.log2(TINY) and pf[0, 1] == np.log2(TINY)
+    assert pf[0, 2] == 0.0 and pf[0, 3] == np.log2(10) and pf[0, 4] == 0.0
 
 
 def test_coincident_group_uses_the_cell_above_the_bucket():
@@ -103,3 +107,27 @@ def test_coincident_group_uses_the_cell_above_the_bucket():
         assert np.isfinite(f[g]).all()
         # every group's first ancestor is the root (the buckets are skipped)
         assert np.isclose(f[g, 4], np.log2(8.0 / count[g]))
+
+
+def test_probe_features_of_two_distant_clusters():
+    """At theta = 1 each cluster sees the other as one cell: its list is its
+    own 4 particles plus that cell."""
+    rng = np.random.default_rng(4)
+    pos = np.concatenate([_cluster([0.0, 0.0, 0.0], rng), _cluster([1.0, 1.0, 1.0], rng)])
+    mass = rng.uniform(0.5, 1.5, 8)
+    t = oracle.Tree(pos, mass)
+    assert t.groups(4) == 2
+    eps = 1e-2
+    f = all_features(t, eps)
+    first, count, lo, hi = t.group_info()
+    _, perm = t.sorted()
+    for g in range(2):
+        own = np.sort(perm[first[g]:first[g] + count[g]])
+        other = np.setdiff1d(np.arange(8), own)
+        cen = (pos[own].min(axis=0) + pos[own].max(axis=0)) / 2
+        mo = mass[other].sum()
+        d = (mass[other][:, None] * pos[other]).sum(axis=0) / mo - cen
+        r2 = d @ d + eps * eps
+        a = mo * np.linalg.norm(d) / r2 ** 1.5
+        exp = [np.log2(a + TINY), np.log2(mo / r2 + TINY), 0.0, np.log2(5.0), 0.0]
+        assert np.allclose(f[g, 6:11], exp, rtol=1e-12, atol=1e-12), (g, f[g, 6:11], exp)
