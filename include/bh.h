@@ -217,9 +217,9 @@ bh_status bh_energy(bh_ctx *ctx, int64_t n, const double *vel, const double *mas
  * 12 group features -> tanh(64) -> tanh(64) -> theta = 0.3 + 0.7 sigmoid(y +
  * shift).  Features (FP32, per group, from the current tree and groups; c the
  * member count, c_g the box centre, R the box half-diagonal, x_g and m_g the
- * members' centre of mass and mass, A1 the smallest cell (not a bucket of
- * equal keys) holding more than c particles, A2 the cell above it (A1 at the
- * root)):
+ * members' centre of mass and mass, A1 the smallest cell with at least two
+ * sub-cells (not a bucket of equal keys) holding more than c particles, A2
+ * the next such cell above it (A1 at the root)):
  *   f0 = log2 c, f1 = log2(1 + R/eps), f2 = |x_g - c_g| / (R + eps),
  *   f3 = log2(l(A1) / (R + eps)), f4 = log2(m(A1) / m_g),
  *   f5 = |com(A1) - c_g| / l(A1), f11 = log2(m(A2) / m_g)

@@ -350,7 +350,7 @@ void bh_destroy(bh_ctx *c) {
                     &c->hist, &c->nodes, &c->msum, &c->meta, &c->levels, &c->lcells, &c->gflag, &c->gidx, &c->glen, &c->ginfo, &c->gbox, &c->glist,
                     &c->gmass, &c->bbox_part, &c->sys, &c->par, &c->info, &c->direct_part, &c->energy_part,
                     &c->glists, &c->far_pool, &c->near_pool, &c->far_next, &c->near_next,
-                    &c->items, &c->item_n, &c->item_off, &c->feps, &c->mlp_work, &c->mlp_feat};
+                    &c->items, &c->item_n, &c->item_off, &c->feps, &c->mlp_work, &c->mlp_feat, &c->order_hist, &c->walk_order, &c->item_order};
   for (DevBuf *b : bufs) free_buf(*b);
   if (c->info_host) (void)hipHostFree(c->info_host);
   if (c->stage) (void)hipHostFree(c->stage);
@@ -490,6 +490,15 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
     c->walk_bpc = walk_lists_blocks_per_cu();
     c->force_bpc = force_lists_blocks_per_cu();
   }
+  const size_t gcap = (size_t)std::max<int64_t>(c->n, 1);
+  const size_t icap = gcap + gcap / 64 + 64;  // force items: at most one per 64 members plus one per group
+  st = ensure(c, c->order_hist, order_hist_bytes(), "queue order bins");
+  if (st) return st;
+  st = ensure(c, c->walk_order, sizeof(int32_t) * gcap, "walk order");
+  if (st) return st;
+  st = ensure(c, c->item_order, sizeof(int32_t) * icap, "force order");
+  if (st) return st;
+  W.order = P<int32_t>(c->walk_order);
   const int grid = c->num_cu * (c->opt.waves_per_cu > 0 ? c->opt.waves_per_cu : c->walk_bpc);
   const int fgrid = c->num_cu * (c->opt.waves_per_cu > 0 ? c->opt.waves_per_cu : c->force_bpc);
   for (int attempt = 0;; ++attempt) {
@@ -513,6 +522,9 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
     reset_list_counters(P<DevInfo>(c->info), c->stream);
     st = timer_start(c, c->t_walk);
     if (st) return st;
+    walk_order_device(P<int32_t>(c->ginfo), P<DevInfo>(c->info), (int64_t)gcap, P<int32_t>(c->order_hist),
+                      P<int32_t>(c->walk_order), c->num_cu, c->stream);
+    if (st) return st;
     walk_lists_device(W, grid, c->stream);
     st = timer_stop(c, c->t_walk);
     if (st) return st;
@@ -529,8 +541,7 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
     c->far_cap = std::max(c->far_cap, (int32_t)(c->info_host->far_chunks + c->info_host->far_chunks / 4 + 64));
     c->near_cap = std::max(c->near_cap, (int32_t)(c->info_host->near_chunks + c->info_host->near_chunks / 4 + 64));
   }
-  const size_t gcap = (size_t)std::max<int64_t>(c->n, 1);
-  st = ensure(c, c->items, 2 * sizeof(int32_t) * (gcap + gcap / 64 + 64), "force items");
+  st = ensure(c, c->items, 2 * sizeof(int32_t) * icap, "force items");
   if (st) return st;
   st = ensure(c, c->item_n, sizeof(int32_t) * gcap, "force item counts");
   if (st) return st;
@@ -554,8 +565,11 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
   F.acc = acc;
   F.pot = pot;
   F.info = P<DevInfo>(c->info);
+  F.order = P<int32_t>(c->item_order);
   st = timer_start(c, c->t_force);
   if (st) return st;
+  item_order_device(P<int32_t>(c->ginfo), P<int32_t>(c->glists), P<int32_t>(c->items), P<DevInfo>(c->info),
+                    (int64_t)icap, P<int32_t>(c->order_hist), P<int32_t>(c->item_order), c->num_cu, c->stream);
   force_lists_device(F, fgrid, c->stream);
   st = timer_stop(c, c->t_force);
   if (st) return st;
@@ -708,7 +722,7 @@ static bh_status features_common(bh_ctx *c, const double *eps_sys, float *feat) 
   a.eps = P<double>(c->feps);
   a.info = P<DevInfo>(c->info);
   a.feat = feat;
-  group_features_device(a, c->n, c->stream);
+  group_features_device(a, c->n, c->num_cu, c->stream);
   ProbeArgs pa{};
   pa.nodes = P<NodeRec>(c->nodes);
   pa.ginfo = P<int32_t>(c->ginfo);

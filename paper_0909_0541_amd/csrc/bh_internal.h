@@ -160,6 +160,8 @@ struct bh_ctx {
   bh::DevBuf feps;              // FP64 [nsys] softening of the feature call
   bh::DevBuf mlp_work;          // training batch workspace
   bh::DevBuf mlp_feat;          // FP32 [n][12] features of bh_group_theta
+  bh::DevBuf order_hist;        // int32 cost bins of the queue orders
+  bh::DevBuf walk_order, item_order;  // int32 queue position -> group / force item
   std::vector<double> feps_host;
   bh::DevInfo *info_host = nullptr;  // pinned mirror
   std::vector<bh::SysInfo> sys_host;
@@ -263,8 +265,16 @@ struct WalkListArgs {
   int32_t *glists;
   int32_t *glist;
   double *gmass;
+  const int32_t *order;  // queue position -> group (longest first)
 };
 void walk_lists_device(const WalkListArgs &a, int grid, hipStream_t s);
+// k_order.hip: longest-first queue orders of the walk and force kernels
+size_t order_hist_bytes();
+void walk_order_device(const int32_t *ginfo, const DevInfo *info, int64_t cap, int32_t *hist, int32_t *order,
+                       int num_cu, hipStream_t s);
+void item_order_device(const int32_t *ginfo, const int32_t *glists, const int32_t *items, const DevInfo *info,
+                       int64_t cap, int32_t *hist, int32_t *order, int num_cu, hipStream_t s);
+
 // probe walk at theta = 1 for the learned-theta features f6..f10
 struct ProbeArgs {
   const NodeRec *nodes;
@@ -297,6 +307,7 @@ struct ForceArgs {
   float *pot;
   DevInfo *info;
   const int32_t *items;  // [n_items][2] group, member block
+  const int32_t *order;  // queue position -> item (longest first)
 };
 void force_items_device(const int32_t *ginfo, DevInfo *info, int64_t cap, int32_t *nblk, int32_t *off,
                         int32_t *items, void *scan_tmp, hipStream_t s);
@@ -333,7 +344,7 @@ struct FeatureArgs {
 struct MlpWork {  // per-sample activations and gradients of a training batch
   float *xn, *h1, *h2, *dz1, *dz2, *dy, *loss, *wsum;
 };
-void group_features_device(const FeatureArgs &a, int64_t cap, hipStream_t s);
+void group_features_device(const FeatureArgs &a, int64_t cap, int num_cu, hipStream_t s);
 void mlp_infer_device(const float *params, const float *mu, const float *sigma, const float *x, int64_t rows,
                       int64_t cap_rows, const DevInfo *info, float shift, float *theta, hipStream_t s);
 void mlp_grad_device(const float *params, const float *mu, const float *sigma, int B, const float *x,

@@ -146,8 +146,9 @@ __global__ __launch_bounds__(kWave) void k_force_lists(ForceArgs a, const float4
   const int lane = lane_id();
   const int T = a.info->n_items;
   for (;;) {
-    const int it = take_one(&a.info->queue2, lane);
-    if (it >= T) break;
+    const int qi = take_one(&a.info->queue2, lane);
+    if (qi >= T) break;
+    const int it = a.order ? __builtin_amdgcn_readfirstlane(a.order[qi]) : qi;
     const int g = items[2 * it], blk = items[2 * it + 1];
     const int gf = a.ginfo[3 * g], gc = a.ginfo[3 * g + 1], gs = a.ginfo[3 * g + 2];
     const int fh = glists[4 * g], fn = glists[4 * g + 1], nh = glists[4 * g + 2], nn = glists[4 * g + 3];

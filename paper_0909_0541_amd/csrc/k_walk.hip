@@ -75,8 +75,9 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
   const int nslots = a.nsys + a.info->n_slots;
 
   for (;;) {
-    const int g = take_one(&a.info->queue, lane);
-    if (g >= G) break;
+    const int gi = take_one(&a.info->queue, lane);
+    if (gi >= G) break;
+    const int g = a.order ? __builtin_amdgcn_readfirstlane(a.order[gi]) : gi;
 
     const int gc = a.ginfo[3 * g + 1], gs = a.ginfo[3 * g + 2];
     double blo[3], bhi[3], cen[3];
@@ -238,10 +239,13 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
 __global__ void k_reset_queue(DevInfo *info) { info->queue = 0; }
 
 // Probe walk of the learned-theta features: the group walk at theta = 1 (the
-// same opening test and traversal as k_walk_lists), summing over the entries
-// instead of writing them: the field and its scale at the box centre from the
-// entries outside the box, the count of single particles among them, the list
-// length and the mass of the entries inside the box.  Writes features f6..f10.
+// traversal of k_walk_lists) with two shortcuts, summing over the entries
+// instead of writing them.  A node that holds only members of the group is
+// taken whole as inside mass, and a cell smaller than the box half-diagonal
+// R is taken whole (as a monopole) without the opening test.  Sums: the field
+// and its scale at the box centre from the entries whose centre of mass lies
+// outside the box, the count of single particles among them, the number of
+// entries and the mass inside the box.  Writes features f6..f10.
 __global__ __launch_bounds__(kWave) void k_probe(ProbeArgs a) {
   __shared__ int2 stk[kStack];
   __shared__ int mark[kWave];
@@ -261,6 +265,13 @@ __global__ __launch_bounds__(kWave) void k_probe(ProbeArgs a) {
     }
     const double eps = a.eps[gs];
     const double eps2 = __dmul_rn(eps, eps);
+    double hd2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double e = __dsub_rn(bhi[k], blo[k]);
+      hd2 = __dadd_rn(hd2, __dmul_rn(e, e));
+    }
+    const double lmin = sqrt(hd2) / 2.0;  // cells smaller than the box half-diagonal are not opened
     double ax = 0.0, ay = 0.0, az = 0.0, S = 0.0, m_in = 0.0;
     int n_part = 0, nlist = 0;
     bool corrupt = false;
@@ -312,7 +323,9 @@ __global__ __launch_bounds__(kWave) void k_probe(ProbeArgs a) {
           const double ek = fmax(0.0, fmax(below, above));
           d2 = (k == 0) ? __dmul_rn(ek, ek) : __dadd_rn(d2, __dmul_rn(ek, ek));
         }
-        if (r.child < 0) {
+        // a node holding only members counts as inside and is not opened
+        const bool member = r.first >= gf && r.first + r.count <= gf + gc;
+        if (member || r.child < 0 || r.l < lmin) {
           emit = true;
         } else {
           const double q = __dadd_rn(r.l, r.s);  // l / theta + s at theta = 1
@@ -320,7 +333,7 @@ __global__ __launch_bounds__(kWave) void k_probe(ProbeArgs a) {
           else push = true;
         }
         if (emit) {
-          if (d2 == 0.0) {
+          if (member || d2 == 0.0) {
             m_in = __dadd_rn(m_in, r.m);
           } else {
             const double dx = __dsub_rn(r.com[0], cen[0]), dy = __dsub_rn(r.com[1], cen[1]),

@@ -10,12 +10,14 @@ module trains the network of ``k_mlp.hip`` to pick theta per group:
 1. *Labels.*  For a snapshot, a seeded sample of groups is evaluated at every
    theta of a ladder (0.3 ... 1.0) on the GPU, together with FP64 direct
    forces for their members.  Per group and theta this gives the cost
-   c_g(theta) = members x (list length - 1) and the error
+   c_g(theta) = list length x (walk weight + member-block passes), a model of
+   the group's walk and force-sum time, and the error
    e_g(theta) = sum over members of |a - a_direct|^2 / |a_direct|^2.
    The theta per group that minimises total cost under a total error budget
    (RMS over the sampled particles equal to the target) follows from the
-   Lagrangian: theta_g = argmin_theta c_g(theta) + lambda e_g(theta), with
-   lambda bisected until the budget is met.
+   Lagrangian min c_g(theta) + lambda e_g(theta), with each group's curves
+   smoothed by power laws over the ladder and lambda bisected until the
+   budget is met (`allocate`).
 2. *Training.*  The network is fitted to these labels (weighted by member
    count) with the library's FP32 forward/backward and Adam kernels.
 3. *Calibration.*  At use, a shift of the network's output is bisected until
@@ -59,6 +61,24 @@ def _dev(a, dtype=torch.float32):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
 
 
+WALK_WEIGHT = 2.0  # walk time per list entry / force time per entry and lane pass (measured)
+
+
+def group_passes(c: int) -> float:
+    """Time of a group per list entry, in force-kernel lane passes: the walk
+    (WALK_WEIGHT) plus one pass per member block of at most 64, divided by
+    the lane partitions a small block uses (as the force kernel splits them)."""
+    nb = (c + 63) // 64
+    total = WALK_WEIGHT
+    for b in range(nb):
+        m = c * (b + 1) // nb - c * b // nb
+        R = 1
+        while R < 64 and m * 2 * R <= 64:
+            R *= 2
+        total += 1.0 / R
+    return total
+
+
 def group_tables(ctx: bh.Context, dpos, dmass, eps: float, n_crit: int, n_sample: int, seed: int,
                  ladder=LADDER):
     """Features, costs and errors of a seeded sample of groups over a theta ladder.
@@ -83,6 +103,7 @@ def group_tables(ctx: bh.Context, dpos, dmass, eps: float, n_crit: int, n_sample
     a_dir = a_dir.cpu().numpy()
     nd = np.linalg.norm(a_dir, axis=1)
     nd = np.where(nd > 0, nd, np.inf)
+    passes = np.array([group_passes(int(c)) for c in count])
     K = len(ladder)
     cost = np.zeros((S, K))
     err = np.zeros((S, K))
@@ -95,7 +116,7 @@ def group_tables(ctx: bh.Context, dpos, dmass, eps: float, n_crit: int, n_sample
         amag[:, k] = np.bincount(owner, weights=np.linalg.norm(a, axis=1), minlength=S) / count
         _, _, ll, _ = ctx.export_groups(lists=True)
         ll = ll.cpu().numpy()[sel].astype(np.float64)
-        cost[:, k] = count * (ll - 1.0)
+        cost[:, k] = ll * passes
     adir = np.bincount(owner, weights=np.linalg.norm(a_dir, axis=1), minlength=S) / count
     return {"feat": feat[sel], "count": count, "cost": cost, "err": err, "ladder": np.asarray(ladder),
             "amag": amag, "adir": adir}

@@ -91,9 +91,9 @@ def test_whole_system_group_has_no_ancestor():
     assert f[0, 0] == np.log2(10)
     assert np.all(f[0, 3:] == 0.0)
     pf = probe_features(t, 0.01)
-    # no entry lies outside the box of a whole system: no field, list = all particles
+    # a whole system is one member node: no field, one entry, inside mass = m_g
     assert pf[0, 0] == np.log2(TINY) and pf[0, 1] == np.log2(TINY)
-    assert pf[0, 2] == 0.0 and pf[0, 3] == np.log2(10) and pf[0, 4] == 0.0
+    assert pf[0, 2] == 0.0 and pf[0, 3] == 0.0 and pf[0, 4] == 0.0
 
 
 def test_coincident_group_uses_the_cell_above_the_bucket():
@@ -110,8 +110,8 @@ def test_coincident_group_uses_the_cell_above_the_bucket():
 
 
 def test_probe_features_of_two_distant_clusters():
-    """At theta = 1 each cluster sees the other as one cell: its list is its
-    own 4 particles plus that cell."""
+    """At theta = 1 each cluster sees the other as one cell, and its own
+    cluster is one member node: two entries."""
     rng = np.random.default_rng(4)
     pos = np.concatenate([_cluster([0.0, 0.0, 0.0], rng), _cluster([1.0, 1.0, 1.0], rng)])
     mass = rng.uniform(0.5, 1.5, 8)
@@ -129,5 +129,5 @@ def test_probe_features_of_two_distant_clusters():
         d = (mass[other][:, None] * pos[other]).sum(axis=0) / mo - cen
         r2 = d @ d + eps * eps
         a = mo * np.linalg.norm(d) / r2 ** 1.5
-        exp = [np.log2(a + TINY), np.log2(mo / r2 + TINY), 0.0, np.log2(5.0), 0.0]
+        exp = [np.log2(a + TINY), np.log2(mo / r2 + TINY), 0.0, 1.0, 0.0]
         assert np.allclose(f[g, 6:11], exp, rtol=1e-12, atol=1e-12), (g, f[g, 6:11], exp)
