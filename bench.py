@@ -64,12 +64,15 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--waves-per-cu", type=int, default=None)
+    ap.add_argument("--theta", type=float, default=None,
+                    help="time this fixed theta (no calibration, no learned leg)")
     ap.add_argument("--target-rms", type=float, default=1e-3,
                     help="calibrate theta by bisection to this RMS force error before timing "
                          "(0: time the workload's own theta)")
     ap.add_argument("--theta-net", default=os.path.join(ROOT, "paper_0909_0541_amd", "theta_net.npz"),
                     help="trained per-group theta network (the learned leg is skipped when missing)")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-systems leg")
     ap.add_argument("--copy-check-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the timed steps, "
                          "as the reference kernel that scales HBM byte counters")
@@ -127,6 +130,33 @@ def _cpu_model():
     return "unknown"
 
 
+def batch_leg(args):
+    """64 independent systems of uneven size (Plummer spheres and clustered
+    boxes, N log-uniform in [1024, 262144], theta = 0.7, eps = N^(-1/3)/20) as
+    one captured HIP graph per step, n_crit and waves per CU autotuned."""
+    import torch
+
+    from paper_0909_0541_amd import autotune, inputs
+
+    pos, mass, off, eps = inputs.batch_systems()
+    dpos = torch.as_tensor(pos, device="cuda")
+    dmass = torch.as_tensor(mass, device="cuda")
+    theta = 0.7
+    best, trials, ctx = autotune.autotune(off, dpos, dmass, eps, theta)
+    ms = autotune.time_graph(ctx, args.steps, args.warmup)
+    st = ctx.get_stats()
+    acc = ctx._graph_io[2]
+    n = int(off[-1])
+    return {"workload": "batch_64", "systems": int(len(off) - 1), "n": n, "theta": theta,
+            "n_crit": best.n_crit, "waves_per_cu": best.waves_per_cu, "ms_per_step": ms,
+            "interactions_per_step": st.interactions, "interactions_per_s": st.interactions / (ms * 1e-3),
+            "particles_per_s": n / (ms * 1e-3),
+            "rms_force_error": autotune.batch_rms(ctx, off, dpos, dmass, eps, acc, sample=args.judge_sample),
+            "step": "one HIP graph replay: build of all 64 trees, groups, list walk, force sum",
+            "autotune": [{"n_crit": t.n_crit, "waves_per_cu": t.waves_per_cu, "ms": t.ms_per_step}
+                         for t in trials]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -148,8 +178,8 @@ def main():
     fixed = learned.Stepper(ctx, dpos, dmass, w.eps, w.n_crit)
 
     calib = None
-    theta = w.theta
-    if args.target_rms > 0:
+    theta = w.theta if args.theta is None else args.theta
+    if args.target_rms > 0 and args.theta is None:
         def rms_of(th):
             fixed(theta=th)
             return judge.rms(fixed.acc)
@@ -238,8 +268,10 @@ def main():
             "interactions_per_s": st2.interactions / (ms2 * 1e-3), "particles_per_s": n / (ms2 * 1e-3),
             "interactions_per_step": st2.interactions, "stage_ms": s2,
             "force_kernel_tflops": FLOPS_PER_INTERACTION * st2.interactions / (s2["force"] * 1e-3) / 1e12}
+    if not args.no_batch:
+        line["batch"] = batch_leg(args)
     if not args.no_cpu_baseline:
-        w_cpu = w if calib is None else dataclasses.replace(w, theta=theta)
+        w_cpu = dataclasses.replace(w, theta=theta)
         line["cpu_baseline"] = cpu_baseline(pos, mass, w_cpu, inter, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 

@@ -171,6 +171,30 @@ bh_status bh_compute_forces(bh_ctx *ctx, double eps, double theta, const float *
 bh_status bh_compute_forces_batch(bh_ctx *ctx, const double *eps_sys, const double *theta_sys,
                                   const float *theta_group, float *acc, float *pot);
 
+/* ---- captured steps (HIP graph) ---------------------------------------- */
+
+/* Record one whole step -- tree build (single system or batch), groups, list
+ * walk and force sum -- into a HIP graph owned by the context, for replay by
+ * bh_graph_launch without host work.  Arguments as for bh_build_batch,
+ * bh_make_groups and bh_compute_forces_batch (eps_sys, theta_sys host FP64
+ * [n_systems]; theta_group device FP32, nullable).  The call first runs the
+ * step eagerly (which sizes every buffer and leaves the results in acc/pot),
+ * grows the list pools by a quarter for replays on moved particles, then
+ * captures.  A replay reads pos and mass where they were at capture (update
+ * them in place between replays) and writes acc and pot.  Sizes, offsets,
+ * n_crit, eps and theta are those of the capture.  A replay cannot wait for
+ * the list-pool check: if a list does not fit, bh_sync (or bh_get_stats)
+ * reports it and the replay's forces are invalid; capture again.  A later
+ * call on the context that has to grow a buffer (a larger input, for one)
+ * discards the capture.  Synchronises (the eager step). */
+bh_status bh_graph_capture(bh_ctx *ctx, int32_t n_systems, const int64_t *offsets, const double *pos,
+                           const double *mass, int32_t n_crit, const double *eps_sys, const double *theta_sys,
+                           const float *theta_group, float *acc, float *pot);
+
+/* Replay the captured step on the context's stream (asynchronous).
+ * BH_ESTATE without a capture. */
+bh_status bh_graph_launch(bh_ctx *ctx);
+
 /* Counters of the current tree, groups and last force call, and the timings
  * collected since the previous call (which are then reset).  Synchronises.
  * stats host, not NULL. */

@@ -75,6 +75,8 @@ def load():
         "bh_compute_forces_batch": ([vp, vp, vp, vp, vp, vp], C.c_int),
         "bh_leapfrog": ([vp, i64, vp, vp, vp, C.c_double, C.c_double, i32, C.c_double, i32, vp, vp], C.c_int),
         "bh_get_stats": ([vp, C.POINTER(_Stats)], C.c_int),
+        "bh_graph_capture": ([vp, i32, vp, vp, vp, i32, vp, vp, vp, vp, vp], C.c_int),
+        "bh_graph_launch": ([vp], C.c_int),
         "bh_group_features": ([vp, vp, vp], C.c_int),
         "bh_mlp_infer": ([vp, C.POINTER(_Mlp), i64, vp, C.c_float, vp], C.c_int),
         "bh_group_theta": ([vp, C.POINTER(_Mlp), vp, C.c_float, vp], C.c_int),
@@ -243,6 +245,37 @@ class Context:
                                                     t.ctypes.data_as(C.c_void_p), _ptr(theta_group), _ptr(acc),
                                                     _ptr(pot)))
         return acc, pot
+
+    def graph_capture(self, offsets, pos: torch.Tensor, mass: torch.Tensor, n_crit: int, eps_sys, theta_sys,
+                      theta_group=None, acc=None, pot=None):
+        """Record one whole step into a HIP graph (runs it once eagerly first);
+        returns (acc, pot), which every graph_launch() rewrites."""
+        import numpy as np
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        ns = len(off) - 1
+        n = int(off[-1])
+        e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps_sys, dtype=np.float64), (ns,)))
+        t = np.ascontiguousarray(np.broadcast_to(np.asarray(theta_sys, dtype=np.float64), (ns,)))
+        _dev(pos, torch.float64, (n, 3), "pos")
+        _dev(mass, torch.float64, (n,), "mass")
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if acc is None:
+            acc = torch.empty((n, 3), dtype=torch.float32, device=dev)
+        if pot is None:
+            pot = torch.empty((n,), dtype=torch.float32, device=dev)
+        _dev(acc, torch.float32, (n, 3), "acc")
+        _dev(pot, torch.float32, (n,), "pot")
+        if theta_group is not None:
+            _dev(theta_group, torch.float32, None, "theta_group")
+        self._check(self._L.bh_graph_capture(self._h, ns, off.ctypes.data_as(C.c_void_p), _ptr(pos), _ptr(mass),
+                                             int(n_crit), e.ctypes.data_as(C.c_void_p), t.ctypes.data_as(C.c_void_p),
+                                             _ptr(theta_group), _ptr(acc), _ptr(pot)))
+        self.n, self.n_systems = n, ns
+        self._graph_io = (pos, mass, acc, pot, theta_group)  # keep the captured buffers alive
+        return acc, pot
+
+    def graph_launch(self):
+        self._check(self._L.bh_graph_launch(self._h))
 
     def get_stats(self) -> Stats:
         s = _Stats()

@@ -97,6 +97,11 @@ bh_status hip_check(bh_ctx *c, hipError_t e, const char *what) {
 bh_status ensure(bh_ctx *c, DevBuf &b, size_t bytes, const char *what) {
   if (bytes == 0) bytes = 16;
   if (b.bytes >= bytes) return BH_OK;
+  if (c->capturing) return fail(c, BH_EINTERNAL, std::string("buffer growth while capturing: ") + what);
+  if (c->graph) {  // the captured step points at the buffer about to move
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
   if (b.p) {
     hipError_t e = hipFree(b.p);
     if (e != hipSuccess) return hip_check(c, e, "hipFree");
@@ -127,7 +132,7 @@ static T *P(DevBuf &b) {
 
 static bh_status timer_start(bh_ctx *c, Timer &t) {
   t.open = false;
-  if (!c->opt.timing) return BH_OK;
+  if (!c->opt.timing || c->capturing) return BH_OK;
   if (t.used >= 4096) return BH_OK;  // bounded: later calls of a long run are not timed
   while ((int)t.ev.size() < 2 * (t.used + 1)) {
     hipEvent_t e;
@@ -163,6 +168,7 @@ static double timer_take(Timer &t, int32_t *calls) {
 // buffer is reused only after the previous upload has completed.
 static bh_status upload(bh_ctx *c, void *dst, const void *src, size_t bytes) {
   if (bytes == 0) return BH_OK;
+  if (c->capturing) return BH_OK;  // the eager run before the capture left the same data on the device
   bh_status st;
   if (c->stage_event_used) {
     st = hip_check(c, hipEventSynchronize(c->stage_event), "hipEventSynchronize");
@@ -352,6 +358,8 @@ void bh_destroy(bh_ctx *c) {
                     &c->glists, &c->far_pool, &c->near_pool, &c->far_next, &c->near_next,
                     &c->items, &c->item_n, &c->item_off, &c->feps, &c->mlp_work, &c->mlp_feat, &c->order_hist, &c->walk_order, &c->item_order};
   for (DevBuf *b : bufs) free_buf(*b);
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   if (c->info_host) (void)hipHostFree(c->info_host);
   if (c->stage) (void)hipHostFree(c->stage);
   if (c->stage_event) (void)hipEventDestroy(c->stage_event);
@@ -478,6 +486,7 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
   }
   WalkListArgs W{};
   W.nodes = P<NodeRec>(c->nodes);
+  W.sys = P<SysInfo>(c->sys);
   W.ginfo = P<int32_t>(c->ginfo);
   W.gbox = P<double>(c->gbox);
   W.par = P<SysParam>(c->par);
@@ -530,7 +539,9 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
     if (st) return st;
     st = hip_check(c, hipGetLastError(), "kernel launch (walk)");
     if (st) return st;
-    // the pools must have held every list before the sums may run
+    // the pools must have held every list before the sums may run; a captured
+    // step cannot wait here: an overflow then leaves kErrPool for bh_sync
+    if (c->capturing) break;
     st = hip_check(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(DevInfo), hipMemcpyDeviceToHost, c->stream),
                    "hipMemcpyAsync info");
     if (st) return st;
@@ -594,6 +605,72 @@ bh_status bh_compute_forces_batch(bh_ctx *c, const double *eps_sys, const double
   if (!c->have_tree) return fail(c, BH_ESTATE, "forces requested before a tree was built");
   if (!eps_sys || !theta_sys) return fail(c, BH_EINVAL, "eps_sys and theta_sys must not be NULL");
   return forces_common(c, eps_sys, theta_sys, theta_group, acc, pot);
+}
+
+bh_status bh_graph_capture(bh_ctx *c, int32_t n_systems, const int64_t *offsets, const double *pos,
+                           const double *mass, int32_t n_crit, const double *eps_sys, const double *theta_sys,
+                           const float *theta_group, float *acc, float *pot) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (n_systems < 1 || n_systems > 65536 || !offsets || !eps_sys || !theta_sys)
+    return fail(c, BH_EINVAL, "bad graph capture arguments");
+  if (offsets[0] != 0) return fail(c, BH_EINVAL, "offsets[0] must be 0");
+  for (int s = 0; s < n_systems; ++s)
+    if (offsets[s + 1] < offsets[s]) return fail(c, BH_EINVAL, "offsets must be non-decreasing");
+  if (n_crit < 1 || n_crit > BH_MAX_NCRIT) return fail(c, BH_EINVAL, "n_crit must be in [1, 256]");
+  // 1. one eager step sizes every buffer and checks the arguments
+  bh_status st = build_common(c, n_systems, offsets, pos, mass);
+  if (!st) st = bh_make_groups(c, n_crit, nullptr);
+  if (!st) st = forces_common(c, eps_sys, theta_sys, theta_group, acc, pot);
+  if (!st) st = bh_sync(c);
+  if (st) return st;
+  // 2. headroom in the list pools for replays on moved particles
+  c->far_cap += c->far_cap / 4;
+  c->near_cap += c->near_cap / 4;
+  st = forces_common(c, eps_sys, theta_sys, theta_group, acc, pot);
+  if (!st) st = bh_sync(c);
+  if (st) return st;
+  // 3. record the same launches on a capture stream
+  if (!c->capture_stream) {
+    st = hip_check(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking), "hipStreamCreate");
+    if (st) return st;
+  }
+  if (c->graph) {
+    (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  hipStream_t saved = c->stream;
+  c->stream = c->capture_stream;
+  c->capturing = true;
+  st = hip_check(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  if (!st) {
+    bh_status sr = build_common(c, n_systems, offsets, pos, mass);
+    if (!sr) sr = bh_make_groups(c, n_crit, nullptr);
+    if (!sr) sr = forces_common(c, eps_sys, theta_sys, theta_group, acc, pot);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    c->capturing = false;
+    c->stream = saved;
+    if (sr) {
+      if (g) (void)hipGraphDestroy(g);
+      return sr;
+    }
+    st = hip_check(c, e, "hipStreamEndCapture");
+    if (!st) st = hip_check(c, hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+    if (g) (void)hipGraphDestroy(g);
+    if (st) c->graph = nullptr;
+    return st;
+  }
+  c->capturing = false;
+  c->stream = saved;
+  return st;
+}
+
+bh_status bh_graph_launch(bh_ctx *c) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (!c->graph) return fail(c, BH_ESTATE, "no captured step");
+  return hip_check(c, hipGraphLaunch(c->graph, c->stream), "hipGraphLaunch");
 }
 
 bh_status bh_get_stats(bh_ctx *c, bh_stats *out) {

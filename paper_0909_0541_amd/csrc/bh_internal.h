@@ -112,6 +112,9 @@ struct bh_ctx {
   bool have_tree = false;
   bool have_groups = false;
   bool have_forces = false;
+  bool capturing = false;         // recording a step into a HIP graph: no uploads, syncs or timers
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t graph = nullptr; // the captured step
   int32_t n_crit = 0;
   int64_t cap_n = 0;  // particle capacity of the per-particle buffers
 
@@ -251,6 +254,7 @@ void reset_force_counters(DevInfo *info, hipStream_t s);
 // k_walk.hip: group walk writing the interaction lists
 struct WalkListArgs {
   const NodeRec *nodes;
+  const SysInfo *sys;
   const int32_t *ginfo;
   const double *gbox;
   const SysParam *par;

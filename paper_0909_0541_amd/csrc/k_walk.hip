@@ -29,7 +29,7 @@ namespace bh {
 
 namespace {
 
-constexpr int kStack = 512;       // range stack entries
+constexpr int kStack = 1024;      // range stack entries
 constexpr int kReserve = 8 * 24;  // growth bound of the stack in one-range mode
 
 // The block is one wavefront: a barrier orders its LDS writes and reads.
@@ -92,6 +92,11 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
       if (lane == 0) atomicOr(&a.info->err, kErrTheta);
       theta = (theta > 1.0) ? 1.0 : 0.0;
     }
+    // A cell's side is the root side times 2^-level exactly, so l / theta =
+    // (side / theta) * 2^-level exactly: one division per group.
+    const double side = a.sys[gs].side;
+    const double side_theta = side / theta;
+    const int side_exp = ilogb(side);
     double hd2 = 0.0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -158,7 +163,7 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
           emit = true;  // a particle
         } else {
           // Eq. (2)/(3): far enough iff d^2 > (l/theta + s)^2
-          double q = r.l / theta;
+          double q = isfinite(r.l) ? ldexp(side_theta, ilogb(r.l) - side_exp) : r.l;
           q = __dadd_rn(q, r.s);
           const double seff = __dmul_rn(q, q);
           if (d2 > seff) emit = true;
