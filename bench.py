@@ -39,12 +39,18 @@ FLOPS_PER_INTERACTION = 20      # 3 sub, 3 FMA (r^2), rsqrt, 3 mul, 3 FMA (acc),
 # HBM traffic of the force kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
 # of this script (bytes per interaction, scaled by the counters' reading of a
 # device copy of known size), valid only for the kernel source it was taken on.
-TRAFFIC = {}
+TRAFFIC = {
+    # clustered box, 2,097,152 particles, theta 0.4203125 (the 1e-3 RMS theta):
+    # FETCH_SIZE 3004309.5 KiB x 1.99987 (a 512 MiB device copy reads as
+    # 262160.5 KiB) + WRITE_SIZE 146230.0 KiB x 1.0 (the copy writes 524288 KiB)
+    "clustered_2m": {"theta": 0.4203125, "bytes_per_launch": 6302178051,
+                     "k_force_sha256": "dd0ee55e76c7b3e173907dd2b938265a5efbac74df126f8a7707be92d3e476fb"},
+}
 
 
-def traffic_for(workload, interactions, t_force_ms):
+def traffic_for(workload, theta):
     rec = TRAFFIC.get(workload)
-    if rec is None:
+    if rec is None or abs(rec["theta"] - theta) > 1e-12:
         return None
     src = os.path.join(ROOT, "paper_0909_0541_amd", "csrc", "k_force.hip")
     with open(src, "rb") as f:
@@ -235,7 +241,7 @@ def main():
         "max_list": st.max_list,
         "stage_ms": stage,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": traffic_for(w.name, inter, t_force),
+                     "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": traffic_for(w.name, theta),
                      "kernel": "k_force_lists", "flops_per_interaction": FLOPS_PER_INTERACTION},
         "force_kernel_interactions_per_s": inter / (t_force * 1e-3),
         "walk_plus_force_interactions_per_s": inter / ((stage["walk"] + t_force) * 1e-3),

@@ -529,10 +529,9 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
     W.near_cap = c->near_cap;
     W.glists = P<int32_t>(c->glists);
     reset_list_counters(P<DevInfo>(c->info), c->stream);
-    st = timer_start(c, c->t_walk);
-    if (st) return st;
     walk_order_device(P<int32_t>(c->ginfo), P<DevInfo>(c->info), (int64_t)gcap, P<int32_t>(c->order_hist),
                       P<int32_t>(c->walk_order), c->num_cu, c->stream);
+    st = timer_start(c, c->t_walk);
     if (st) return st;
     walk_lists_device(W, grid, c->stream);
     st = timer_stop(c, c->t_walk);
@@ -577,10 +576,10 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
   F.pot = pot;
   F.info = P<DevInfo>(c->info);
   F.order = P<int32_t>(c->item_order);
-  st = timer_start(c, c->t_force);
-  if (st) return st;
   item_order_device(P<int32_t>(c->ginfo), P<int32_t>(c->glists), P<int32_t>(c->items), P<DevInfo>(c->info),
                     (int64_t)icap, P<int32_t>(c->order_hist), P<int32_t>(c->item_order), c->num_cu, c->stream);
+  st = timer_start(c, c->t_force);
+  if (st) return st;
   force_lists_device(F, fgrid, c->stream);
   st = timer_stop(c, c->t_force);
   if (st) return st;
