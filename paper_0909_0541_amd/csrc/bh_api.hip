@@ -356,7 +356,7 @@ void bh_destroy(bh_ctx *c) {
                     &c->hist, &c->nodes, &c->msum, &c->meta, &c->levels, &c->lcells, &c->gflag, &c->gidx, &c->glen, &c->ginfo, &c->gbox, &c->glist,
                     &c->gmass, &c->bbox_part, &c->sys, &c->par, &c->info, &c->direct_part, &c->energy_part,
                     &c->glists, &c->far_pool, &c->near_pool, &c->far_next, &c->near_next,
-                    &c->items, &c->item_n, &c->item_off, &c->feps, &c->mlp_work, &c->mlp_feat, &c->order_hist, &c->walk_order, &c->item_order};
+                    &c->items, &c->item_n, &c->item_off, &c->feps, &c->mlp_work, &c->mlp_feat, &c->order_hist, &c->item_order};
   for (DevBuf *b : bufs) free_buf(*b);
   if (c->graph) (void)hipGraphExecDestroy(c->graph);
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
@@ -503,11 +503,8 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
   const size_t icap = gcap + gcap / 64 + 64;  // force items: at most one per 64 members plus one per group
   st = ensure(c, c->order_hist, order_hist_bytes(), "queue order bins");
   if (st) return st;
-  st = ensure(c, c->walk_order, sizeof(int32_t) * gcap, "walk order");
-  if (st) return st;
   st = ensure(c, c->item_order, sizeof(int32_t) * icap, "force order");
   if (st) return st;
-  W.order = P<int32_t>(c->walk_order);
   const int grid = c->num_cu * (c->opt.waves_per_cu > 0 ? c->opt.waves_per_cu : c->walk_bpc);
   const int fgrid = c->num_cu * (c->opt.waves_per_cu > 0 ? c->opt.waves_per_cu : c->force_bpc);
   for (int attempt = 0;; ++attempt) {
@@ -529,8 +526,6 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
     W.near_cap = c->near_cap;
     W.glists = P<int32_t>(c->glists);
     reset_list_counters(P<DevInfo>(c->info), c->stream);
-    walk_order_device(P<int32_t>(c->ginfo), P<DevInfo>(c->info), (int64_t)gcap, P<int32_t>(c->order_hist),
-                      P<int32_t>(c->walk_order), c->num_cu, c->stream);
     st = timer_start(c, c->t_walk);
     if (st) return st;
     walk_lists_device(W, grid, c->stream);

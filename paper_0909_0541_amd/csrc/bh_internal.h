@@ -64,6 +64,7 @@ struct DevInfo {
   int32_t near_chunks;
   int32_t n_items;        // force work items (group, member block)
   int32_t pad2;
+  int32_t xq[8];          // walk queue heads, one per XCD
 };
 
 // Interaction lists: chunks of kFarChunk far entries (float4 x - c_g, m) and
@@ -164,7 +165,7 @@ struct bh_ctx {
   bh::DevBuf mlp_work;          // training batch workspace
   bh::DevBuf mlp_feat;          // FP32 [n][12] features of bh_group_theta
   bh::DevBuf order_hist;        // int32 cost bins of the queue orders
-  bh::DevBuf walk_order, item_order;  // int32 queue position -> group / force item
+  bh::DevBuf item_order;        // int32 queue position -> force item (longest first)
   std::vector<double> feps_host;
   bh::DevInfo *info_host = nullptr;  // pinned mirror
   std::vector<bh::SysInfo> sys_host;
@@ -269,13 +270,10 @@ struct WalkListArgs {
   int32_t *glists;
   int32_t *glist;
   double *gmass;
-  const int32_t *order;  // queue position -> group (longest first)
 };
 void walk_lists_device(const WalkListArgs &a, int grid, hipStream_t s);
-// k_order.hip: longest-first queue orders of the walk and force kernels
+// k_order.hip: longest-first queue order of the force kernel
 size_t order_hist_bytes();
-void walk_order_device(const int32_t *ginfo, const DevInfo *info, int64_t cap, int32_t *hist, int32_t *order,
-                       int num_cu, hipStream_t s);
 void item_order_device(const int32_t *ginfo, const int32_t *glists, const int32_t *items, const DevInfo *info,
                        int64_t cap, int32_t *hist, int32_t *order, int num_cu, hipStream_t s);
 

@@ -1,14 +1,13 @@
-// Longest-first processing orders for the persistent walk and force kernels.
+// Longest-first processing order for the persistent force kernel.
 //
-// Both kernels pull work from an atomic queue; when a few long tasks are
-// pulled last, the grid idles while they finish.  Ordering the queue by a
-// cost estimate, longest first, bounds that tail (list scheduling).  The
-// order is a counting sort over integer cost bins (descending); ties keep no
-// particular order, which does not change any result: every task computes
-// its own outputs independently.
-//   walk:  cost bin = member count of the group (larger groups walk longer);
-//   force: cost bin = (far entries + 2 near entries) / partitions / 64, the
-//          passes one item makes over its lists.
+// The kernel pulls work items from an atomic queue; when a few long items are
+// pulled last, the grid idles while they finish.  Ordering the queue by cost,
+// longest first, bounds that tail (list scheduling).  The order is a counting
+// sort over integer cost bins (descending): cost bin = (far entries + 2 near
+// entries) / lane partitions / 64, the passes one item makes over its lists.
+// Each block ranks one tile of items per bin in LDS and takes one run of
+// positions per non-empty bin from the global cursors.  The order within a
+// bin does not change any result: every item computes its own outputs.
 #include <algorithm>
 
 #include "bh_device.h"
@@ -18,10 +17,7 @@ namespace bh {
 namespace {
 
 constexpr int kBins = 1024;
-
-__device__ __forceinline__ int walk_key(const int32_t *ginfo, int64_t g) {
-  return min(ginfo[3 * g + 1], kBins - 1);
-}
+constexpr int kTile = 2048;  // items ranked per block
 
 __device__ __forceinline__ int item_key(const int32_t *ginfo, const int32_t *glists, const int32_t *items,
                                         int64_t it) {
@@ -36,29 +32,22 @@ __device__ __forceinline__ int item_key(const int32_t *ginfo, const int32_t *gli
   return (int)min<int64_t>(cost >> 6, kBins - 1);
 }
 
-__device__ __forceinline__ int count_of(const DevInfo *info, int mode) {
-  return mode == 0 ? info->n_groups : info->n_items;
-}
-
-__device__ __forceinline__ int key_of(int mode, const int32_t *ginfo, const int32_t *glists, const int32_t *items,
-                                      int64_t i) {
-  return mode == 0 ? walk_key(ginfo, i) : item_key(ginfo, glists, items, i);
-}
-
 __global__ void k_order_clear(int32_t *hist) {
   for (int b = threadIdx.x; b < kBins; b += blockDim.x) hist[b] = 0;
 }
 
-__global__ void k_order_hist(int mode, const int32_t *__restrict__ ginfo, const int32_t *__restrict__ glists,
-                             const int32_t *__restrict__ items, const DevInfo *__restrict__ info, int64_t cap,
-                             int32_t *__restrict__ hist) {
+__global__ __launch_bounds__(256) void k_order_hist(const int32_t *__restrict__ ginfo,
+                                                    const int32_t *__restrict__ glists,
+                                                    const int32_t *__restrict__ items,
+                                                    const DevInfo *__restrict__ info, int64_t cap,
+                                                    int32_t *__restrict__ hist) {
   __shared__ int32_t h[kBins];
   for (int b = threadIdx.x; b < kBins; b += blockDim.x) h[b] = 0;
   __syncthreads();
-  const int64_t n = count_of(info, mode);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n && i < cap;
-       i += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&h[kBins - 1 - key_of(mode, ginfo, glists, items, i)], 1);
+  const int64_t n = min<int64_t>(info->n_items, cap);
+  const int64_t t0 = (int64_t)blockIdx.x * kTile;
+  for (int64_t i = t0 + threadIdx.x; i < n && i < t0 + kTile; i += blockDim.x)
+    atomicAdd(&h[kBins - 1 - item_key(ginfo, glists, items, i)], 1);
   __syncthreads();
   for (int b = threadIdx.x; b < kBins; b += blockDim.x)
     if (h[b]) atomicAdd(&hist[b], h[b]);
@@ -77,39 +66,49 @@ __global__ __launch_bounds__(kBins) void k_order_scan(int32_t *hist) {
   hist[t] = off + inc - v;
 }
 
-__global__ void k_order_scatter(int mode, const int32_t *__restrict__ ginfo, const int32_t *__restrict__ glists,
-                                const int32_t *__restrict__ items, const DevInfo *__restrict__ info, int64_t cap,
-                                int32_t *__restrict__ cursor, int32_t *__restrict__ order) {
-  const int64_t n = count_of(info, mode);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n && i < cap;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int b = kBins - 1 - key_of(mode, ginfo, glists, items, i);
-    order[atomicAdd(&cursor[b], 1)] = (int32_t)i;
+__global__ __launch_bounds__(256) void k_order_scatter(const int32_t *__restrict__ ginfo,
+                                                       const int32_t *__restrict__ glists,
+                                                       const int32_t *__restrict__ items,
+                                                       const DevInfo *__restrict__ info, int64_t cap,
+                                                       int32_t *__restrict__ cursor, int32_t *__restrict__ order) {
+  __shared__ int32_t cnt[kBins], base[kBins];
+  __shared__ int16_t key[kTile];
+  const int64_t n = min<int64_t>(info->n_items, cap);
+  const int64_t t0 = (int64_t)blockIdx.x * kTile;
+  if (t0 >= n) return;
+  const int tn = (int)min<int64_t>(kTile, n - t0);
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x) cnt[b] = 0;
+  __syncthreads();
+  for (int k = threadIdx.x; k < tn; k += blockDim.x) {
+    const int b = kBins - 1 - item_key(ginfo, glists, items, t0 + k);
+    key[k] = (int16_t)b;
+    atomicAdd(&cnt[b], 1);
   }
-}
-
-void order_device(int mode, const int32_t *ginfo, const int32_t *glists, const int32_t *items, const DevInfo *info,
-                  int64_t cap, int32_t *hist, int32_t *order, int num_cu, hipStream_t s) {
-  if (cap <= 0) return;
-  const unsigned grid = (unsigned)std::min<int64_t>((cap + 255) / 256, (int64_t)num_cu * 4);
-  k_order_clear<<<1, 256, 0, s>>>(hist);
-  k_order_hist<<<grid, 256, 0, s>>>(mode, ginfo, glists, items, info, cap, hist);
-  k_order_scan<<<1, kBins, 0, s>>>(hist);
-  k_order_scatter<<<grid, 256, 0, s>>>(mode, ginfo, glists, items, info, cap, hist, order);
+  __syncthreads();
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x) base[b] = cnt[b] ? atomicAdd(&cursor[b], cnt[b]) : 0;
+  __syncthreads();
+  // one thread per bin walks the tile in index order
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x) {
+    if (!cnt[b]) continue;
+    int pos = base[b];
+    for (int k = 0; k < tn; ++k)
+      if (key[k] == b) order[pos++] = (int32_t)(t0 + k);
+  }
 }
 
 }  // namespace
 
 size_t order_hist_bytes() { return sizeof(int32_t) * kBins; }
 
-void walk_order_device(const int32_t *ginfo, const DevInfo *info, int64_t cap, int32_t *hist, int32_t *order,
-                       int num_cu, hipStream_t s) {
-  order_device(0, ginfo, nullptr, nullptr, info, cap, hist, order, num_cu, s);
-}
-
 void item_order_device(const int32_t *ginfo, const int32_t *glists, const int32_t *items, const DevInfo *info,
                        int64_t cap, int32_t *hist, int32_t *order, int num_cu, hipStream_t s) {
-  order_device(1, ginfo, glists, items, info, cap, hist, order, num_cu, s);
+  (void)num_cu;
+  if (cap <= 0) return;
+  const unsigned grid = (unsigned)((cap + kTile - 1) / kTile);
+  k_order_clear<<<1, 256, 0, s>>>(hist);
+  k_order_hist<<<grid, 256, 0, s>>>(ginfo, glists, items, info, cap, hist);
+  k_order_scan<<<1, kBins, 0, s>>>(hist);
+  k_order_scatter<<<grid, 256, 0, s>>>(ginfo, glists, items, info, cap, hist, order);
 }
 
 }  // namespace bh

@@ -1,8 +1,8 @@
 // Group walk that builds the interaction lists (Fig. "treewalk" for a group,
 // Eq. 2/3; the interaction-list method of Sec. 3.2).
 //
-// One wavefront per group, persistent grid pulling groups from an atomic
-// queue.  The wave walks the tree in batches of up to 64 nodes taken from a
+// One wavefront per group, persistent grid pulling groups from atomic
+// queues.  The wave walks the tree in batches of up to 64 nodes taken from a
 // stack of slot ranges (a cell's children occupy consecutive slots) kept in
 // LDS.  Each lane tests one node with the FP64 opening test
 // d^2 > (l/theta + s)^2, d = distance from the cell's centre of mass to the
@@ -18,11 +18,13 @@
 //
 // Stack bound: a batch pops up to 64 nodes and pushes at most one range per
 // node.  While the stack is high, the wave takes only the top range (at most 8
-// cells), which is a depth-first walk: at most 8 ranges per level above the
-// point where it started, at most 23 levels.  Batches of 64 are taken only
-// while at least 64 + 8 * 24 free entries remain, so the stack never exceeds
-// its capacity; an overflow check still guards every push, and an iteration
-// budget (a tree visits each slot once) bounds the walk of every group.
+// cells) after the previous batch has pushed, which is a depth-first walk: at
+// most 8 ranges per level above the point where it started, at most 23
+// levels.  Batches of 64 are taken (ahead of the pushes of the batch in
+// flight) only while at least 2 * 64 + 8 * 24 free entries remain, so the
+// stack never exceeds its capacity; an overflow check still guards every
+// push, and an iteration budget (a tree visits each slot once, and a batch
+// is handled in two iterations) bounds the walk of every group.
 #include "bh_device.h"
 
 namespace bh {
@@ -74,10 +76,25 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
   const int G = a.info->n_groups;
   const int nslots = a.nsys + a.info->n_slots;
 
+  // Groups are taken in Morton order from eight contiguous eighths, one per
+  // XCD (workgroups go to the XCDs round robin), so that the waves sharing an
+  // L2 walk neighbouring groups and read mostly the same nodes; a wave whose
+  // eighth is done takes from the others.
+  const int xcd = blockIdx.x & 7;
+  int tried = 0;
   for (;;) {
-    const int gi = take_one(&a.info->queue, lane);
-    if (gi >= G) break;
-    const int g = a.order ? __builtin_amdgcn_readfirstlane(a.order[gi]) : gi;
+    int g = -1;
+    while (tried < 8) {
+      const int x = (xcd + tried) & 7;
+      const int s0 = (int)((int64_t)G * x / 8), s1 = (int)((int64_t)G * (x + 1) / 8);
+      const int t = take_one(&a.info->xq[x], lane);
+      if (s0 + t < s1) {
+        g = s0 + t;
+        break;
+      }
+      ++tried;
+    }
+    if (g < 0) break;
 
     const int gc = a.ginfo[3 * g + 1], gs = a.ginfo[3 * g + 2];
     double blo[3], bhi[3], cen[3];
@@ -109,108 +126,127 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
     ChunkList F, N;
     bool fok = true, nok = true, corrupt = false;
     int sp = 1, nlist = 0;
-    int budget = 2 * nslots + 2;
+    int budget = 4 * nslots + 4;
     double lmass = 0.0;
     if (lane == 0) stk[0] = make_int2(gs, 1);
     wave_sync();
-    while (sp > 0) {
+    // Software pipeline: the records of the next batch are loaded while the
+    // current batch is tested, so that one batch's memory latency hides
+    // behind the other's work.  The next batch is taken from the stack before
+    // the current batch pushes its children, except when the stack is high:
+    // then the walk is the plain depth-first one of the stack bound above.
+    int bcur = 0;
+    NodeRec rcur;
+    for (;;) {
       if (--budget < 0) {
         corrupt = true;
         break;
       }
-      const bool starved = sp > kStack - kWave - kReserve;
-      const int nread = starved ? 1 : min(sp, kWave);
-      int2 e = make_int2(0, 0);
-      if (lane < nread) e = stk[sp - 1 - lane];
-      const int cnt = (lane < nread) ? e.y : 0;
-      const int pre = wave_inclusive_sum(cnt);
-      const int total = __shfl(pre, nread - 1, kWave);
-      const int B = min(starved ? 8 : kWave, total);
-      const int start = pre - cnt;
-      const int kfull = __popcll(__ballot(lane < nread && pre <= B));
-      mark[lane] = -1;
-      wave_sync();
-      if (lane < nread && start < B) mark[start] = lane;
-      wave_sync();
-      const int ei = wave_inclusive_max(mark[lane]);
-      const int e_start = __shfl(start, ei < 0 ? 0 : ei, kWave);
-      const int e_first = __shfl(e.x, ei < 0 ? 0 : ei, kWave);
-      const int nsp = sp - kfull;
-      if (kfull < nread) {
-        const int pstart = __shfl(start, kfull, kWave);
-        if (pstart < B && lane == kfull) stk[sp - 1 - kfull] = make_int2(e.x + (B - pstart), e.y - (B - pstart));
+      int bnext = 0, node = 0;
+      const bool starved = sp > kStack - 2 * kWave - kReserve;
+      if (sp > 0 && (bcur == 0 || !starved)) {
+        const int nread = starved ? 1 : min(sp, kWave);
+        int2 e = make_int2(0, 0);
+        if (lane < nread) e = stk[sp - 1 - lane];
+        const int cnt = (lane < nread) ? e.y : 0;
+        const int pre = wave_inclusive_sum(cnt);
+        const int total = __shfl(pre, nread - 1, kWave);
+        bnext = min(starved ? 8 : kWave, total);
+        const int start = pre - cnt;
+        const int kfull = __popcll(__ballot(lane < nread && pre <= bnext));
+        mark[lane] = -1;
+        wave_sync();
+        if (lane < nread && start < bnext) mark[start] = lane;
+        wave_sync();
+        const int ei = wave_inclusive_max(mark[lane]);
+        const int e_start = __shfl(start, ei < 0 ? 0 : ei, kWave);
+        const int e_first = __shfl(e.x, ei < 0 ? 0 : ei, kWave);
+        const int nsp = sp - kfull;
+        if (kfull < nread) {
+          const int pstart = __shfl(start, kfull, kWave);
+          if (pstart < bnext && lane == kfull)
+            stk[sp - 1 - kfull] = make_int2(e.x + (bnext - pstart), e.y - (bnext - pstart));
+        }
+        sp = nsp;  // the partly taken range (if any) stays on the stack
+        node = e_first + (lane - e_start);
+        if (__ballot(lane < bnext && (node < 0 || node >= nslots))) {
+          corrupt = true;  // corrupt range: report, never read out of bounds
+          break;
+        }
       }
-      const int node = e_first + (lane - e_start);
-      if (__ballot(lane < B && (node < 0 || node >= nslots))) {
-        corrupt = true;  // corrupt range: report, never read out of bounds
-        break;
-      }
-      bool emit = false, push = false, near = false;
-      float4 hi4 = make_float4(0.f, 0.f, 0.f, 0.f), lo4 = hi4;
-      int2 rng = make_int2(0, 0);
-      if (lane < B) {
-        const NodeRec r = a.nodes[node];
-        // squared distance from the centre of mass to the group's box
-        double d2 = 0.0;
+      NodeRec rnext;
+      if (lane < bnext) rnext = a.nodes[node];
+      if (bcur > 0) {
+        bool emit = false, push = false, near = false;
+        float4 hi4 = make_float4(0.f, 0.f, 0.f, 0.f), lo4 = hi4;
+        int2 rng = make_int2(0, 0);
+        if (lane < bcur) {
+          const NodeRec &r = rcur;
+          // squared distance from the centre of mass to the group's box
+          double d2 = 0.0;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const double below = __dsub_rn(blo[k], r.com[k]);
-          const double above = __dsub_rn(r.com[k], bhi[k]);
-          const double ek = fmax(0.0, fmax(below, above));
-          d2 = (k == 0) ? __dmul_rn(ek, ek) : __dadd_rn(d2, __dmul_rn(ek, ek));
+          for (int k = 0; k < 3; ++k) {
+            const double below = __dsub_rn(blo[k], r.com[k]);
+            const double above = __dsub_rn(r.com[k], bhi[k]);
+            const double ek = fmax(0.0, fmax(below, above));
+            d2 = (k == 0) ? __dmul_rn(ek, ek) : __dadd_rn(d2, __dmul_rn(ek, ek));
+          }
+          if (r.child < 0) {
+            emit = true;  // a particle
+          } else {
+            // Eq. (2)/(3): far enough iff d^2 > (l/theta + s)^2
+            double q = isfinite(r.l) ? ldexp(side_theta, ilogb(r.l) - side_exp) : r.l;
+            q = __dadd_rn(q, r.s);
+            const double seff = __dmul_rn(q, q);
+            if (d2 > seff) emit = true;
+            else push = true;
+          }
+          if (emit) {
+            const double rx = __dsub_rn(r.com[0], cen[0]), ry = __dsub_rn(r.com[1], cen[1]),
+                         rz = __dsub_rn(r.com[2], cen[2]);
+            hi4 = make_float4((float)rx, (float)ry, (float)rz, (float)r.m);
+            near = d2 <= near2;
+            if (near)
+              lo4 = make_float4((float)__dsub_rn(rx, (double)hi4.x), (float)__dsub_rn(ry, (double)hi4.y),
+                                (float)__dsub_rn(rz, (double)hi4.z), 0.0f);
+            lmass += r.m;
+          }
+          if (push) rng = make_int2(r.child, r.nchild);
         }
-        if (r.child < 0) {
-          emit = true;  // a particle
-        } else {
-          // Eq. (2)/(3): far enough iff d^2 > (l/theta + s)^2
-          double q = isfinite(r.l) ? ldexp(side_theta, ilogb(r.l) - side_exp) : r.l;
-          q = __dadd_rn(q, r.s);
-          const double seff = __dmul_rn(q, q);
-          if (d2 > seff) emit = true;
-          else push = true;
+        const unsigned long long em = __ballot(emit), pm = __ballot(push);
+        const unsigned long long nm = __ballot(emit && near), fm = em & ~nm;
+        const int npush = __popcll(pm);
+        if (sp + npush > kStack) {
+          corrupt = true;
+          break;
         }
-        if (emit) {
-          const double rx = __dsub_rn(r.com[0], cen[0]), ry = __dsub_rn(r.com[1], cen[1]),
-                       rz = __dsub_rn(r.com[2], cen[2]);
-          hi4 = make_float4((float)rx, (float)ry, (float)rz, (float)r.m);
-          near = d2 <= near2;
-          if (near)
-            lo4 = make_float4((float)__dsub_rn(rx, (double)hi4.x), (float)__dsub_rn(ry, (double)hi4.y),
-                              (float)__dsub_rn(rz, (double)hi4.z), 0.0f);
-          lmass += r.m;
+        if (push) stk[sp + rank_below(pm)] = rng;
+        const int nf = __popcll(fm), nn = __popcll(nm);
+        if (nf > 0) {
+          fok = reserve(F, nf, kFarChunk, &a.info->far_chunks, a.far_cap, a.far_next, lane, fok);
+          if (fok && emit && !near) {
+            const int pos = F.count + rank_below(fm);
+            a.far_pool[(int64_t)chunk_of(F, pos, kFarChunk) * kFarChunk + pos % kFarChunk] = hi4;
+          }
+          F.count += nf;
         }
-        if (push) rng = make_int2(r.child, r.nchild);
-      }
-      const unsigned long long em = __ballot(emit), pm = __ballot(push);
-      const unsigned long long nm = __ballot(emit && near), fm = em & ~nm;
-      const int npush = __popcll(pm);
-      if (nsp + npush > kStack) {
-        corrupt = true;
-        break;
-      }
-      if (push) stk[nsp + rank_below(pm)] = rng;
-      const int nf = __popcll(fm), nn = __popcll(nm);
-      if (nf > 0) {
-        fok = reserve(F, nf, kFarChunk, &a.info->far_chunks, a.far_cap, a.far_next, lane, fok);
-        if (fok && emit && !near) {
-          const int pos = F.count + rank_below(fm);
-          a.far_pool[(int64_t)chunk_of(F, pos, kFarChunk) * kFarChunk + pos % kFarChunk] = hi4;
+        if (nn > 0) {
+          nok = reserve(N, nn, kNearChunk, &a.info->near_chunks, a.near_cap, a.near_next, lane, nok);
+          if (nok && emit && near) {
+            const int pos = N.count + rank_below(nm);
+            float4 *base = a.near_pool + (int64_t)chunk_of(N, pos, kNearChunk) * (2 * kNearChunk);
+            base[pos % kNearChunk] = hi4;
+            base[kNearChunk + pos % kNearChunk] = lo4;
+          }
+          N.count += nn;
         }
-        F.count += nf;
-      }
-      if (nn > 0) {
-        nok = reserve(N, nn, kNearChunk, &a.info->near_chunks, a.near_cap, a.near_next, lane, nok);
-        if (nok && emit && near) {
-          const int pos = N.count + rank_below(nm);
-          float4 *base = a.near_pool + (int64_t)chunk_of(N, pos, kNearChunk) * (2 * kNearChunk);
-          base[pos % kNearChunk] = hi4;
-          base[kNearChunk + pos % kNearChunk] = lo4;
-        }
-        N.count += nn;
+        nlist += nf + nn;
+        sp += npush;
       }
       wave_sync();
-      nlist += nf + nn;
-      sp = nsp + npush;
+      bcur = bnext;
+      rcur = rnext;
+      if (bcur == 0 && sp == 0) break;
     }
     if (corrupt) {
       if (lane == 0) {
