@@ -84,11 +84,21 @@ typedef struct {
   int32_t n_groups_calls;
   int32_t n_walk_calls;
   int32_t n_force_calls;
+  int32_t n_split_groups;  /* last force call: groups whose walk was handed over to several waves */
+  int32_t n_segments;      /* last force call: list segments of those groups */
+  int32_t n_split_levels;  /* last force call: deepest hand-over level of a split walk (0: none) */
+  int32_t n_walk_attempts; /* last force call: walks run (more than 1 when a list pool had to grow) */
 } bh_stats;
 
 typedef struct {
   int32_t waves_per_cu;  /* persistent grids = CUs x waves_per_cu; 0 (default): as many as fit */
   int32_t timing;        /* 1: record HIP events around each stage (default 0) */
+  int32_t split_visits;  /* a group walk that has tested this many nodes hands the rest of its
+                            stack to up to 16 new walk tasks, which waves with no group left
+                            take in the same launch, so that long lists are walked and summed
+                            by several waves; tasks 5 hand-overs deep walk to the end (0:
+                            default 12288; -1: never; else >= 64).  Results do not depend on
+                            when or where the tasks ran, only on this value. */
 } bh_options;
 
 /* ---- context ---------------------------------------------------------- */

@@ -37,7 +37,9 @@ class _Stats(C.Structure):
                 ("list_entries", C.c_int64), ("max_list", C.c_int64), ("max_level", C.c_int32),
                 ("error_flags", C.c_int32), ("t_build_ms", C.c_double), ("t_groups_ms", C.c_double),
                 ("t_walk_ms", C.c_double), ("t_force_ms", C.c_double), ("n_build_calls", C.c_int32),
-                ("n_groups_calls", C.c_int32), ("n_walk_calls", C.c_int32), ("n_force_calls", C.c_int32)]
+                ("n_groups_calls", C.c_int32), ("n_walk_calls", C.c_int32), ("n_force_calls", C.c_int32),
+                ("n_split_groups", C.c_int32), ("n_segments", C.c_int32), ("n_split_levels", C.c_int32),
+                ("n_walk_attempts", C.c_int32)]
 
 
 class _Mlp(C.Structure):
@@ -48,7 +50,7 @@ MLP_FEATURES, MLP_HIDDEN, MLP_PARAMS = 12, 64, 5057
 
 
 class _Options(C.Structure):
-    _fields_ = [("waves_per_cu", C.c_int32), ("timing", C.c_int32)]
+    _fields_ = [("waves_per_cu", C.c_int32), ("timing", C.c_int32), ("split_visits", C.c_int32)]
 
 
 def load():
@@ -135,13 +137,17 @@ class Stats:
     n_groups_calls: int
     n_walk_calls: int
     n_force_calls: int
+    n_split_groups: int
+    n_segments: int
+    n_split_levels: int
+    n_walk_attempts: int
 
 
 class Context:
     """A bh_ctx bound to a torch stream (the current stream by default)."""
 
     def __init__(self, stream: torch.cuda.Stream | None = None, waves_per_cu: int | None = None,
-                 timing: bool = False):
+                 timing: bool = False, split_visits: int | None = None):
         self._L = load()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: libbh runs only on the device")
@@ -156,6 +162,8 @@ class Context:
         if waves_per_cu is not None:
             opt.waves_per_cu = int(waves_per_cu)
         opt.timing = 1 if timing else 0
+        if split_visits is not None:
+            opt.split_visits = int(split_visits)
         self._check(self._L.bh_set_options(self._h, C.byref(opt)))
 
     def _check(self, st, h=0):
@@ -176,13 +184,16 @@ class Context:
         except Exception:
             pass
 
-    def set_options(self, waves_per_cu: int | None = None, timing: bool | None = None):
+    def set_options(self, waves_per_cu: int | None = None, timing: bool | None = None,
+                    split_visits: int | None = None):
         opt = _Options()
         self._check(self._L.bh_get_options(self._h, C.byref(opt)))
         if waves_per_cu is not None:
             opt.waves_per_cu = int(waves_per_cu)
         if timing is not None:
             opt.timing = 1 if timing else 0
+        if split_visits is not None:
+            opt.split_visits = int(split_visits)
         self._check(self._L.bh_set_options(self._h, C.byref(opt)))
 
     def sync(self):

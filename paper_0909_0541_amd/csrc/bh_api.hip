@@ -247,6 +247,7 @@ static bh_status check_device_errors(bh_ctx *c) {
   if (e & kErrBuild) return fail(c, BH_EINTERNAL, "tree build produced an inconsistent node layout");
   if (e & kErrStack) return fail(c, BH_EINTERNAL, "walk stack capacity exceeded or node range corrupt");
   if (e & kErrPool) return fail(c, BH_EINTERNAL, "interaction list pool exhausted");
+  if (e & kErrWait) return fail(c, BH_EINTERNAL, "walk task wait timed out");
   return BH_OK;
 }
 
@@ -338,11 +339,23 @@ bh_status bh_create(bh_ctx **out, void *stream) {
     delete c;
     return BH_EHIP;
   }
+  // a walk wave waits at most 2 s for a task (a guard: a task comes within
+  // milliseconds, the length of the longest walk unit)
+  int clock_khz = 0;
+  if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, c->device) != hipSuccess || clock_khz <= 0)
+    clock_khz = 100000;
+  c->wait_ticks = (long long)clock_khz * 2000;
   if (hipHostMalloc((void **)&c->info_host, sizeof(DevInfo), 0) != hipSuccess) {
     delete c;
     return BH_ENOMEM;
   }
   memset(c->info_host, 0, sizeof(DevInfo));
+  if (hipHostMalloc((void **)&c->split_host, sizeof(SplitCounters), 0) != hipSuccess) {
+    (void)hipHostFree(c->info_host);
+    delete c;
+    return BH_ENOMEM;
+  }
+  memset(c->split_host, 0, sizeof(SplitCounters));
   *out = c;
   return BH_OK;
 }
@@ -356,12 +369,15 @@ void bh_destroy(bh_ctx *c) {
                     &c->hist, &c->nodes, &c->msum, &c->meta, &c->levels, &c->lcells, &c->gflag, &c->gidx, &c->glen, &c->ginfo, &c->gbox, &c->glist,
                     &c->gmass, &c->bbox_part, &c->sys, &c->par, &c->info, &c->direct_part, &c->energy_part,
                     &c->glists, &c->far_pool, &c->near_pool, &c->far_next, &c->near_next,
-                    &c->items, &c->item_n, &c->item_off, &c->feps, &c->mlp_work, &c->mlp_feat, &c->order_hist, &c->item_order};
+                    &c->items, &c->item_n, &c->item_off, &c->feps, &c->mlp_work, &c->mlp_feat, &c->order_hist, &c->item_order, &c->tasks, &c->ranges, &c->segs,
+                    &c->split_ctr, &c->gsplit, &c->gnseg, &c->gsegfirst, &c->skeys[0], &c->skeys[1], &c->svals[0],
+                    &c->svals[1], &c->shist, &c->sscan, &c->srows, &c->spbase, &c->sgroups, &c->psum};
   for (DevBuf *b : bufs) free_buf(*b);
   if (c->graph) (void)hipGraphExecDestroy(c->graph);
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   if (c->info_host) (void)hipHostFree(c->info_host);
   if (c->stage) (void)hipHostFree(c->stage);
+  if (c->split_host) (void)hipHostFree(c->split_host);
   if (c->stage_event) (void)hipEventDestroy(c->stage_event);
   Timer *ts[] = {&c->t_build, &c->t_groups, &c->t_walk, &c->t_force};
   for (Timer *t : ts)
@@ -386,6 +402,8 @@ bh_status bh_get_options(const bh_ctx *c, bh_options *opt) {
 bh_status bh_set_options(bh_ctx *c, const bh_options *opt) {
   if (!c || !opt) return BH_EINVAL;
   if (opt->waves_per_cu < 0 || opt->waves_per_cu > 32) return fail(c, BH_EINVAL, "waves_per_cu must be in [0, 32]");
+  if (opt->split_visits < -1 || (opt->split_visits > 0 && opt->split_visits < 64))
+    return fail(c, BH_EINVAL, "split_visits must be -1, 0 or >= 64");
   c->opt = *opt;
   return BH_OK;
 }
@@ -500,13 +518,19 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
     c->force_bpc = force_lists_blocks_per_cu();
   }
   const size_t gcap = (size_t)std::max<int64_t>(c->n, 1);
-  const size_t icap = gcap + gcap / 64 + 64;  // force items: at most one per 64 members plus one per group
+  // split walks (long lists walked and summed by several waves)
+  const int visit_cap = c->opt.split_visits < 0 ? 0 : (c->opt.split_visits == 0 ? kSplitVisits : c->opt.split_visits);
+  if (c->seg_cap == 0) {
+    c->task_cap = 4096;
+    c->range_cap = 1 << 16;
+    c->seg_cap = 4096;
+  }
   st = ensure(c, c->order_hist, order_hist_bytes(), "queue order bins");
-  if (st) return st;
-  st = ensure(c, c->item_order, sizeof(int32_t) * icap, "force order");
   if (st) return st;
   const int grid = c->num_cu * (c->opt.waves_per_cu > 0 ? c->opt.waves_per_cu : c->walk_bpc);
   const int fgrid = c->num_cu * (c->opt.waves_per_cu > 0 ? c->opt.waves_per_cu : c->force_bpc);
+  SplitBuffers S{};
+  int32_t nsegs_host = 0;
   for (int attempt = 0;; ++attempt) {
     st = ensure(c, c->far_pool, (size_t)c->far_cap * kFarChunk * sizeof(float4), "far list pool");
     if (st) return st;
@@ -516,8 +540,21 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
     if (st) return st;
     st = ensure(c, c->near_next, (size_t)c->near_cap * sizeof(int32_t), "near list links");
     if (st) return st;
-    st = ensure(c, c->glists, (size_t)4 * sizeof(int32_t) * (size_t)std::max<int64_t>(c->n, 1), "group lists");
+    st = ensure(c, c->glists, (size_t)4 * sizeof(int32_t) * gcap, "group lists");
     if (st) return st;
+    const size_t sc = (size_t)c->seg_cap;
+    DevBuf *sb[] = {&c->tasks, &c->ranges, &c->segs, &c->split_ctr, &c->gsplit, &c->gnseg,
+                    &c->gsegfirst, &c->skeys[0], &c->skeys[1], &c->svals[0], &c->svals[1], &c->shist,
+                    &c->sscan, &c->srows, &c->spbase, &c->sgroups};
+    const size_t sz[] = {sizeof(WalkTask) * (size_t)c->task_cap,
+                         sizeof(int2) * (size_t)c->range_cap, sizeof(Segment) * sc, sizeof(SplitCounters) + 64,
+                         sizeof(int32_t) * gcap, sizeof(int32_t) * gcap, sizeof(int32_t) * gcap, 8 * sc, 8 * sc,
+                         4 * sc, 4 * sc, radix_hist_bytes((int64_t)sc), scan_tmp_bytes((int64_t)sc) + 256,
+                         4 * sc, 4 * sc + 16, 4 * sc};
+    for (int k = 0; k < (int)(sizeof(sz) / sizeof(sz[0])); ++k) {
+      st = ensure(c, *sb[k], sz[k], "split walk buffers");
+      if (st) return st;
+    }
     W.far_pool = P<float4>(c->far_pool);
     W.near_pool = P<float4>(c->near_pool);
     W.far_next = P<int32_t>(c->far_next);
@@ -525,9 +562,21 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
     W.far_cap = c->far_cap;
     W.near_cap = c->near_cap;
     W.glists = P<int32_t>(c->glists);
+    W.ctr = P<SplitCounters>(c->split_ctr);
+    W.tasks = P<WalkTask>(c->tasks);
+    W.task_cap = c->task_cap;
+    W.ranges = P<int2>(c->ranges);
+    W.range_cap = c->range_cap;
+    W.segs = P<Segment>(c->segs);
+    W.seg_cap = c->seg_cap;
+    W.gsplit = P<int32_t>(c->gsplit);
+    W.visit_cap = visit_cap;
+    W.wait_ticks = c->wait_ticks;
     reset_list_counters(P<DevInfo>(c->info), c->stream);
+    split_reset(W.ctr, P<DevInfo>(c->info), W.tasks, c->task_cap, c->stream);
     st = timer_start(c, c->t_walk);
     if (st) return st;
+    c->last_attempts = attempt + 1;
     walk_lists_device(W, grid, c->stream);
     st = timer_stop(c, c->t_walk);
     if (st) return st;
@@ -539,21 +588,66 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
     st = hip_check(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(DevInfo), hipMemcpyDeviceToHost, c->stream),
                    "hipMemcpyAsync info");
     if (st) return st;
+    if (visit_cap > 0) {
+      st = hip_check(c, hipMemcpyAsync(c->split_host, W.ctr, sizeof(SplitCounters), hipMemcpyDeviceToHost,
+                                       c->stream), "hipMemcpyAsync split counters");
+      if (st) return st;
+    }
     st = hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     if (st) return st;
+    if (visit_cap > 0) nsegs_host = c->split_host->segs;
+    c->last_segments = nsegs_host;
+    c->last_split_groups = visit_cap > 0 ? c->split_host->n_split : 0;
+    c->last_depth = visit_cap > 0 ? c->split_host->depth : 0;
     if (!(c->info_host->err & kErrPool)) break;
-    if (attempt > 0) return fail(c, BH_EINTERNAL, "interaction list pool still too small after growing");
+    if (attempt > 5) return fail(c, BH_EINTERNAL, "interaction list pool still too small after growing");
     c->far_cap = std::max(c->far_cap, (int32_t)(c->info_host->far_chunks + c->info_host->far_chunks / 4 + 64));
     c->near_cap = std::max(c->near_cap, (int32_t)(c->info_host->near_chunks + c->info_host->near_chunks / 4 + 64));
+    if (visit_cap > 0) {
+      const SplitCounters &h = *c->split_host;
+      if (h.tasks > c->task_cap) c->task_cap = std::max(2 * c->task_cap, h.tasks + h.tasks / 4 + 64);
+      if (h.ranges > c->range_cap) c->range_cap = std::max(2 * c->range_cap, h.ranges + h.ranges / 4 + 1024);
+      if (h.segs > c->seg_cap) c->seg_cap = std::max(2 * c->seg_cap, h.segs + h.segs / 4 + 64);
+    }
   }
+  const bool split = visit_cap > 0 && (c->capturing || nsegs_host > 0);
+  S.ctr = P<SplitCounters>(c->split_ctr);
+  S.segs = P<Segment>(c->segs);
+  S.seg_cap = c->seg_cap;
+  S.keys[0] = P<uint64_t>(c->skeys[0]);
+  S.keys[1] = P<uint64_t>(c->skeys[1]);
+  S.vals[0] = P<uint32_t>(c->svals[0]);
+  S.vals[1] = P<uint32_t>(c->svals[1]);
+  S.hist = P<uint32_t>(c->shist);
+  S.scan_tmp = c->sscan.p;
+  S.order = S.vals[0];
+  S.gsegfirst = P<int32_t>(c->gsegfirst);
+  S.gnseg = P<int32_t>(c->gnseg);
+  S.rows = P<int32_t>(c->srows);
+  S.pbase = P<int32_t>(c->spbase);
+  S.total_rows = S.pbase + c->seg_cap;
+  S.sgroups = P<int32_t>(c->sgroups);
+  S.nsg = S.total_rows + 1;
+  if (visit_cap > 0) {  // sized even when nothing split, so that a capture never has to grow it
+    st = ensure(c, c->psum, sizeof(double) * 4 * (size_t)c->seg_cap * (size_t)std::max(c->n_crit, 1), "partial sums");
+    if (st) return st;
+    S.psum = P<double>(c->psum);
+  }
+  if (split)
+    split_finish_device(S, P<int32_t>(c->ginfo), P<int32_t>(c->glist), P<double>(c->gmass), P<DevInfo>(c->info),
+                        c->stream);
+  const size_t icap = gcap + gcap / 64 + 64 + (size_t)4 * c->seg_cap;  // items: blocks of 64, segments
   st = ensure(c, c->items, 2 * sizeof(int32_t) * icap, "force items");
   if (st) return st;
   st = ensure(c, c->item_n, sizeof(int32_t) * gcap, "force item counts");
   if (st) return st;
   st = ensure(c, c->item_off, sizeof(int32_t) * gcap, "force item offsets");
   if (st) return st;
-  force_items_device(P<int32_t>(c->ginfo), P<DevInfo>(c->info), (int64_t)gcap, P<int32_t>(c->item_n),
-                     P<int32_t>(c->item_off), P<int32_t>(c->items), c->scan_tmp.p, c->stream);
+  st = ensure(c, c->item_order, sizeof(int32_t) * icap, "force order");
+  if (st) return st;
+  force_items_device(P<int32_t>(c->ginfo), P<int32_t>(c->gsplit), P<int32_t>(c->gnseg), P<DevInfo>(c->info),
+                     (int64_t)gcap, P<int32_t>(c->item_n), P<int32_t>(c->item_off), P<int32_t>(c->items),
+                     c->scan_tmp.p, c->stream);
   ForceArgs F{};
   F.items = P<int32_t>(c->items);
   F.ginfo = P<int32_t>(c->ginfo);
@@ -571,13 +665,20 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
   F.pot = pot;
   F.info = P<DevInfo>(c->info);
   F.order = P<int32_t>(c->item_order);
-  item_order_device(P<int32_t>(c->ginfo), P<int32_t>(c->glists), P<int32_t>(c->items), P<DevInfo>(c->info),
-                    (int64_t)icap, P<int32_t>(c->order_hist), P<int32_t>(c->item_order), c->num_cu, c->stream);
+  F.segs = S.segs;
+  F.seg_order = S.order;
+  F.gsegfirst = S.gsegfirst;
+  F.pbase = S.pbase;
+  F.psum = split ? P<double>(c->psum) : nullptr;
+  item_order_device(F, (int64_t)icap, P<int32_t>(c->order_hist), P<int32_t>(c->item_order), c->stream);
   st = timer_start(c, c->t_force);
   if (st) return st;
   force_lists_device(F, fgrid, c->stream);
   st = timer_stop(c, c->t_force);
   if (st) return st;
+  if (split)
+    split_reduce_device(S, P<int32_t>(c->ginfo), P<double>(c->smass), P<int32_t>(c->perm), P<SysParam>(c->par), acc,
+                        pot, c->stream);
   st = hip_check(c, hipGetLastError(), "kernel launch (force)");
   if (st) return st;
   c->have_forces = true;
@@ -687,6 +788,10 @@ bh_status bh_get_stats(bh_ctx *c, bh_stats *out) {
     out->interactions = (int64_t)d.interactions;
     out->list_entries = (int64_t)d.list_entries;
     out->max_list = d.max_list;
+    out->n_split_groups = c->last_split_groups;
+    out->n_segments = c->last_segments;
+    out->n_split_levels = c->last_depth;
+    out->n_walk_attempts = c->last_attempts;
   }
   out->t_build_ms = timer_take(c->t_build, &out->n_build_calls);
   out->t_groups_ms = timer_take(c->t_groups, &out->n_groups_calls);

@@ -12,7 +12,11 @@ __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
 // One value per wavefront from an atomic counter: every lane executes the
 // atomic (lane 0 adds one, the others zero) so that no divergent branch
-// precedes the broadcast of lane 0's result.  Call with all lanes active.
+// precedes the broadcast of lane 0's result.  Call with all lanes active and
+// a counter address the compiler can see is the same on every lane (derive
+// a computed index with readfirstlane): only then is the atomic issued as
+// one request; 64 requests on one counter serialise behind each other, which
+// once made the walk ten times slower.
 __device__ __forceinline__ int take_one(int *counter, int lane) {
   const int t = atomicAdd(counter, lane == 0 ? 1 : 0);
   return __builtin_amdgcn_readfirstlane(t);

@@ -82,6 +82,40 @@ enum : int32_t {
   kErrTheta = 8,
   kErrBuild = 16,
   kErrPool = 32,
+  kErrWait = 64,
+};
+
+// Split walks: a walk that has tested split_visits nodes hands its remaining
+// stack to new tasks and ends its own segment of the group's list; waves that
+// find no group left take the tasks, in the same launch.  Segments of a group
+// are summed separately and reduced in the order of their keys: the group's
+// first walk has key 0, and task j of a hand-over by a walk with key K has key
+// 17 K + j + 1, so keys are unique, fixed by the walks alone (not by when or
+// where tasks ran), and below 17^kSplitDepth.
+struct WalkTask {
+  int32_t g;       // group
+  int32_t roff;    // first of its ranges in the range pool
+  int32_t rcount;  // ranges (its initial stack, bottom first); -1 until published
+  int32_t key;     // order of its segment within the group
+};
+struct Segment {
+  int32_t g, key;
+  int32_t fh, fn, nh, nn;  // far/near chunk list heads and entry counts
+  int32_t len, pad;
+  double mass;
+};
+constexpr int kSplitDepth = 5;       // tasks this many hand-overs deep walk to the end
+constexpr int kSplitVisits = 12288;  // default node tests before a walk hands over
+constexpr int kDonateTasks = 16;     // tasks made from one handed-over stack
+struct SplitCounters {               // device
+  int32_t tasks;                     // task slots reserved
+  int32_t queue;                     // task slots claimed by waiting waves
+  int32_t ranges;                    // range pool entries taken
+  int32_t segs;                      // segments written
+  int32_t n_split;                   // groups whose list is in segments
+  int32_t pending;                   // units (groups and published tasks) not finished
+  int32_t depth;                     // deepest hand-over level reached
+  int32_t waiters;                   // waves that wait for tasks
 };
 
 // Growable device buffer.
@@ -104,7 +138,7 @@ struct bh_ctx {
   int device = 0;
   int num_cu = 0;
   std::string err;
-  bh_options opt{0, 0};
+  bh_options opt{0, 0, 0};
   int walk_bpc = 0, force_bpc = 0, probe_bpc = 0;  // resident blocks per CU of the persistent kernels
 
   // current tree
@@ -166,6 +200,14 @@ struct bh_ctx {
   bh::DevBuf mlp_feat;          // FP32 [n][12] features of bh_group_theta
   bh::DevBuf order_hist;        // int32 cost bins of the queue orders
   bh::DevBuf item_order;        // int32 queue position -> force item (longest first)
+  // split walks: tasks (ping-pong), range pool, segments, counters, per-group
+  // flags, segment sort and partial sums
+  bh::DevBuf tasks, ranges, segs, split_ctr, gsplit, gnseg, gsegfirst;
+  bh::DevBuf skeys[2], svals[2], shist, sscan, srows, spbase, sgroups, psum;
+  bh::SplitCounters *split_host = nullptr;  // pinned
+  int32_t task_cap = 0, range_cap = 0, seg_cap = 0;
+  int32_t last_split_groups = 0, last_segments = 0, last_depth = 0, last_attempts = 0;
+  long long wait_ticks = 0;  // wall-clock ticks a walk wave may wait for a task (2 s)
   std::vector<double> feps_host;
   bh::DevInfo *info_host = nullptr;  // pinned mirror
   std::vector<bh::SysInfo> sys_host;
@@ -270,12 +312,41 @@ struct WalkListArgs {
   int32_t *glists;
   int32_t *glist;
   double *gmass;
+  // split walks
+  int visit_cap;             // node tests before a walk hands over its stack (0: never)
+  SplitCounters *ctr;
+  WalkTask *tasks;           // task slots (ctr->tasks reserved)
+  int task_cap;
+  int2 *ranges;
+  int range_cap;
+  Segment *segs;
+  int seg_cap;
+  long long wait_ticks;      // wall-clock ticks a wave may wait for a task
+  int32_t *gsplit;           // per group: 1 when its list is in segments
 };
 void walk_lists_device(const WalkListArgs &a, int grid, hipStream_t s);
+// k_split.hip: ordering and reduction of split groups
+struct SplitBuffers {
+  SplitCounters *ctr;
+  Segment *segs;
+  int seg_cap;
+  uint64_t *keys[2];
+  uint32_t *vals[2];
+  uint32_t *hist;
+  void *scan_tmp;
+  uint32_t *order;            // out: sorted position -> segment
+  int32_t *gsegfirst, *gnseg;  // per group
+  int32_t *rows, *pbase, *total_rows;
+  int32_t *sgroups, *nsg;     // split groups (unordered) and their count
+  double *psum;
+};
+void split_finish_device(SplitBuffers &S, const int32_t *ginfo, int32_t *glist, double *gmass, DevInfo *info,
+                         hipStream_t s);
+void split_reduce_device(const SplitBuffers &S, const int32_t *ginfo, const double *smass, const int32_t *perm,
+                         const SysParam *par, float *acc, float *pot, hipStream_t s);
+void split_reset(SplitCounters *ctr, const DevInfo *info, WalkTask *tasks, int task_cap, hipStream_t s);
 // k_order.hip: longest-first queue order of the force kernel
 size_t order_hist_bytes();
-void item_order_device(const int32_t *ginfo, const int32_t *glists, const int32_t *items, const DevInfo *info,
-                       int64_t cap, int32_t *hist, int32_t *order, int num_cu, hipStream_t s);
 
 // probe walk at theta = 1 for the learned-theta features f6..f10
 struct ProbeArgs {
@@ -308,12 +379,20 @@ struct ForceArgs {
   float *acc;
   float *pot;
   DevInfo *info;
-  const int32_t *items;  // [n_items][2] group, member block
+  const int32_t *items;  // [n_items][2] group, member block (+ 256 x (segment + 1) for a split group)
   const int32_t *order;  // queue position -> item (longest first)
+  // split groups: segments sorted by (group, key), the first sorted segment
+  // of each group, and the partial sums of each segment's members
+  const Segment *segs;
+  const uint32_t *seg_order;  // sorted position -> segment
+  const int32_t *gsegfirst;   // group -> first sorted position
+  const int32_t *pbase;       // sorted position -> first partial-sum row
+  double *psum;               // [rows][4] ax, ay, az, pot
 };
-void force_items_device(const int32_t *ginfo, DevInfo *info, int64_t cap, int32_t *nblk, int32_t *off,
-                        int32_t *items, void *scan_tmp, hipStream_t s);
+void force_items_device(const int32_t *ginfo, const int32_t *gsplit, const int32_t *gnseg, DevInfo *info, int64_t cap,
+                        int32_t *nblk, int32_t *off, int32_t *items, void *scan_tmp, hipStream_t s);
 void force_lists_device(const ForceArgs &a, int grid, hipStream_t s);
+void item_order_device(const ForceArgs &f, int64_t cap, int32_t *hist, int32_t *order, hipStream_t s);
 int force_lists_blocks_per_cu();
 void reset_list_counters(DevInfo *info, hipStream_t s);
 

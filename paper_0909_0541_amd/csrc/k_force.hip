@@ -149,9 +149,25 @@ __global__ __launch_bounds__(kWave) void k_force_lists(ForceArgs a, const float4
     const int qi = take_one(&a.info->queue2, lane);
     if (qi >= T) break;
     const int it = a.order ? __builtin_amdgcn_readfirstlane(a.order[qi]) : qi;
-    const int g = items[2 * it], blk = items[2 * it + 1];
+    const int g = items[2 * it], iv = items[2 * it + 1];
+    const int blk = iv & 255, segl = iv >> 8;
     const int gf = a.ginfo[3 * g], gc = a.ginfo[3 * g + 1], gs = a.ginfo[3 * g + 2];
-    const int fh = glists[4 * g], fn = glists[4 * g + 1], nh = glists[4 * g + 2], nn = glists[4 * g + 3];
+    int fh, fn, nh, nn, prow = -1;
+    if (segl == 0) {
+      fh = glists[4 * g];
+      fn = glists[4 * g + 1];
+      nh = glists[4 * g + 2];
+      nn = glists[4 * g + 3];
+    } else {
+      // one segment of a split group: partial sums go to its rows
+      const int p = a.gsegfirst[g] + segl - 1;
+      const Segment sg = a.segs[a.seg_order[p]];
+      fh = sg.fh;
+      fn = sg.fn;
+      nh = sg.nh;
+      nn = sg.nn;
+      prow = a.pbase[p];
+    }
     if ((fn > 0 && fh < 0) || (nn > 0 && nh < 0)) continue;  // incomplete list (reported by the walk)
     // members [b0, b1) of the group: blocks of near-equal size, at most 64
     const int nb = (gc + kWave - 1) / kWave;
@@ -213,7 +229,15 @@ __global__ __launch_bounds__(kWave) void k_force_lists(ForceArgs a, const float4
       vz += shfl_xor_d(vz, b);
       vp += shfl_xor_d(vp, b);
     }
-    if (part == 0 && u < m) {
+    if (prow >= 0) {
+      if (part == 0 && u < m) {
+        double *q = a.psum + 4 * ((int64_t)prow + b0 + u);
+        q[0] = vx;
+        q[1] = vy;
+        q[2] = vz;
+        q[3] = vp;
+      }
+    } else if (part == 0 && u < m) {
       const int i = gf + b0 + u;
       const float self_ri = __builtin_amdgcn_rsqf(__builtin_fmaf(0.0f, 0.0f, eps2));
       const double self = (double)((float)a.smass[i] * self_ri);
@@ -226,32 +250,44 @@ __global__ __launch_bounds__(kWave) void k_force_lists(ForceArgs a, const float4
   }
 }
 
-// Member blocks per group (ceil(count / 64)).
-__global__ void k_item_counts(const int32_t *__restrict__ ginfo, const DevInfo *__restrict__ info, int64_t cap,
+// Member blocks per group (ceil(count / 64)), times the segments of a split group.
+__global__ void k_item_counts(const int32_t *__restrict__ ginfo, const int32_t *__restrict__ gsplit,
+                              const int32_t *__restrict__ gnseg, const DevInfo *__restrict__ info, int64_t cap,
                               int32_t *__restrict__ nblk) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= cap) return;
-  nblk[g] = (g < info->n_groups) ? (ginfo[3 * g + 1] + kWave - 1) / kWave : 0;
+  int nb = 0;
+  if (g < info->n_groups) {
+    nb = (ginfo[3 * g + 1] + kWave - 1) / kWave;
+    if (gsplit[g]) nb *= gnseg[g];
+  }
+  nblk[g] = nb;
 }
 
-__global__ void k_item_fill(const int32_t *__restrict__ nblk, const int32_t *__restrict__ off,
+// Items as (group, member block + 256 x (segment + 1) for a split group).
+__global__ void k_item_fill(const int32_t *__restrict__ ginfo, const int32_t *__restrict__ gsplit,
+                            const int32_t *__restrict__ gnseg, const int32_t *__restrict__ off,
                             const DevInfo *__restrict__ info, int32_t *__restrict__ items) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= info->n_groups) return;
-  for (int b = 0; b < nblk[g]; ++b) {
-    items[2 * ((int64_t)off[g] + b)] = (int32_t)g;
-    items[2 * ((int64_t)off[g] + b) + 1] = b;
-  }
+  const int nb = (ginfo[3 * g + 1] + kWave - 1) / kWave;
+  const int ns = gsplit[g] ? gnseg[g] : 0;
+  int64_t k = off[g];
+  for (int s = 0; s < (ns ? ns : 1); ++s)
+    for (int b = 0; b < nb; ++b, ++k) {
+      items[2 * k] = (int32_t)g;
+      items[2 * k + 1] = b + (ns ? 256 * (s + 1) : 0);
+    }
 }
 
 }  // namespace
 
-void force_items_device(const int32_t *ginfo, DevInfo *info, int64_t cap, int32_t *nblk, int32_t *off,
-                        int32_t *items, void *scan_tmp, hipStream_t s) {
+void force_items_device(const int32_t *ginfo, const int32_t *gsplit, const int32_t *gnseg, DevInfo *info, int64_t cap,
+                        int32_t *nblk, int32_t *off, int32_t *items, void *scan_tmp, hipStream_t s) {
   const unsigned blocks = (unsigned)((cap + 255) / 256);
-  k_item_counts<<<blocks, 256, 0, s>>>(ginfo, info, cap, nblk);
+  k_item_counts<<<blocks, 256, 0, s>>>(ginfo, gsplit, gnseg, info, cap, nblk);
   scan_exclusive_i32(nblk, off, cap, &info->n_items, scan_tmp, s);
-  k_item_fill<<<blocks, 256, 0, s>>>(nblk, off, info, items);
+  k_item_fill<<<blocks, 256, 0, s>>>(ginfo, gsplit, gnseg, off, info, items);
 }
 
 int force_lists_blocks_per_cu() {

@@ -21,10 +21,17 @@
 // cells) after the previous batch has pushed, which is a depth-first walk: at
 // most 8 ranges per level above the point where it started, at most 23
 // levels.  Batches of 64 are taken (ahead of the pushes of the batch in
-// flight) only while at least 2 * 64 + 8 * 24 free entries remain, so the
-// stack never exceeds its capacity; an overflow check still guards every
-// push, and an iteration budget (a tree visits each slot once, and a batch
-// is handled in two iterations) bounds the walk of every group.
+// flight) only while at least 3 * 64 + 8 * 24 free entries remain (one batch
+// more for a hand-over, below), so the stack never exceeds its capacity; an
+// overflow check still guards every push, and an iteration budget (a tree
+// visits each slot once, and a batch is handled in two iterations) bounds
+// the walk of every group.
+//
+// Split walks: a walk that has tested visit_cap nodes deals the nodes left on
+// its stack to up to 16 tasks and ends its own segment of the group's list;
+// tasks run in the same launch (tasks first, then groups), hand over again
+// up to kSplitDepth levels, and are keyed so that the order in which
+// segments are summed does not depend on when or where they ran.
 #include "bh_device.h"
 
 namespace bh {
@@ -33,6 +40,8 @@ namespace {
 
 constexpr int kStack = 1024;      // range stack entries
 constexpr int kReserve = 8 * 24;  // growth bound of the stack in one-range mode
+constexpr int kTaskStack = 512;   // largest first stack of a task
+constexpr int kWaiters = 64;      // waves that wait for tasks once the groups are taken
 
 // The block is one wavefront: a barrier orders its LDS writes and reads.
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }
@@ -69,6 +78,130 @@ __device__ __forceinline__ int chunk_of(const ChunkList &L, int pos, int chunk) 
   return (pos / chunk == L.cap / chunk - 1) ? L.cur : L.prev;
 }
 
+// Task slots: rcount -1 until published, then the task's range count, or 0
+// for a slot that a hand-over reserved but could not fill (a pool ran out).
+// Wait for slot t: returns its rcount, or -1 when it is still unpublished and
+// no unit is left that could publish it.  The polls are relaxed loads (an
+// acquiring load would invalidate the L2 that the walking waves read their
+// nodes from, on every poll); one acquire fence follows what was seen.
+__device__ __forceinline__ int wait_slot(const WalkListArgs &a, int t, int lane) {
+  const long long t0 = wall_clock64();
+  int r = -1;
+  for (int poll = 0;; ++poll) {
+    const int rc = __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(&a.tasks[t].rcount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (rc >= 0) {
+      r = rc;
+      break;
+    }
+    // every unit publishes its tasks before it leaves the count of pending
+    // units (read every fourth poll: all waiting waves read this one word)
+    const int p = (poll & 3) ? 1 : __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(&a.ctr->pending, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (p <= 0) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      r = __builtin_amdgcn_readfirstlane(
+          __hip_atomic_load(&a.tasks[t].rcount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      break;
+    }
+    if (wall_clock64() - t0 > a.wait_ticks) {
+      if (lane == 0) atomicOr(&a.info->err, kErrWait);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(60);
+  }
+  if (r > 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the task's fields and ranges
+  return r;
+}
+
+// The next unit of a wave: its group, with task >= 0 when it is a task; a
+// negative group when the wave has no more work.  Tasks come first: a task
+// continues a long walk, which is on the critical path of the launch.  A
+// wave that sees a reserved slot no wave has claimed takes a ticket (the
+// next slot number); when the ticket's slot is not yet published the wave
+// walks groups meanwhile and looks at the slot again at the end of each
+// unit, so the claim never blocks while groups are left.  When no group is
+// left, the wave waits for its ticket's slot (taking a ticket if it has
+// none): the waiting waves form a queue in slot order.  Groups are taken in
+// Morton order from eight contiguous eighths, one per XCD (workgroups go to
+// the XCDs round robin), so that the waves sharing an L2 walk neighbouring
+// groups and read mostly the same nodes; a wave whose eighth is done takes
+// from the others.
+__device__ __forceinline__ int next_unit(const WalkListArgs &a, int G, int xcd, int &tried, int &ticket, bool &waiter,
+                                         int &task, int lane) {
+  task = -1;
+  int g = -1;
+  for (;;) {
+    int rc = -1;
+    if (a.visit_cap > 0) {
+      if (ticket < 0) {
+        const int head = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(&a.ctr->queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        const int res = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(&a.ctr->tasks, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (head < min(res, a.task_cap)) ticket = take_one(&a.ctr->queue, lane);
+      }
+      if (ticket >= 0 && ticket < a.task_cap)
+        rc = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(&a.tasks[ticket].rcount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
+    if (rc < 0) {  // no published task at hand: a group
+      while (tried < 8) {
+        const int x = __builtin_amdgcn_readfirstlane((xcd + tried) & 7);
+        const int s0 = (int)((int64_t)G * x / 8), s1 = (int)((int64_t)G * (x + 1) / 8);
+        const int q = take_one(&a.info->xq[x], lane);
+        if (s0 + q < s1) {
+          g = s0 + q;
+          break;
+        }
+        ++tried;
+      }
+      if (g >= 0 || a.visit_cap <= 0) break;
+      if (ticket < 0) {
+        // a bounded number of waves wait for tasks; the others leave (a
+        // wave that holds no ticket owes no slot), which keeps the polling
+        // of the waiting waves from slowing the last walks
+        if (!waiter) {
+          if (take_one(&a.ctr->waiters, lane) >= kWaiters) break;
+          waiter = true;
+        }
+        ticket = take_one(&a.ctr->queue, lane);
+      }
+      if (ticket >= a.task_cap) break;  // no slot beyond the capacity is ever written
+      rc = wait_slot(a, ticket, lane);
+      if (rc < 0) break;
+    } else if (rc > 0) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the task's fields and ranges
+    }
+    const int t = ticket;
+    ticket = -1;
+    if (rc > 0) {
+      g = __builtin_amdgcn_readfirstlane(a.tasks[t].g);
+      if (g >= 0 && g < G) {
+        task = t;
+      } else {  // corrupt: report, retire the unit, stop this wave
+        if (lane == 0) atomicOr(&a.info->err, kErrStack);
+        atomicAdd(&a.ctr->pending, lane == 0 ? -1 : 0);
+        g = -1;
+      }
+      break;
+    }
+    // rc == 0: a slot released empty; look again
+  }
+  return g;
+}
+
+// Hand-over depth of a task from its key (key = 17 K + j + 1, K the parent's).
+__device__ __forceinline__ int key_depth(int key) {
+  int d = 0;
+  for (int k = key; k > 0 && d < 8; k = (k - 1) / (kDonateTasks + 1)) ++d;
+  return d;
+}
+
+// One unit of walk per pass of the outer loop: a group's whole walk, or a
+// task handed over by a walk that reached the visit cap.  Units take chunks
+// for their own list (the group's list unless the walk splits, else a
+// segment).
 __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
   __shared__ int2 stk[kStack];
   __shared__ int mark[kWave];
@@ -76,25 +209,14 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
   const int G = a.info->n_groups;
   const int nslots = a.nsys + a.info->n_slots;
 
-  // Groups are taken in Morton order from eight contiguous eighths, one per
-  // XCD (workgroups go to the XCDs round robin), so that the waves sharing an
-  // L2 walk neighbouring groups and read mostly the same nodes; a wave whose
-  // eighth is done takes from the others.
   const int xcd = blockIdx.x & 7;
-  int tried = 0;
+  int tried = 0, ticket = -1;
+  bool waiter = false;
   for (;;) {
-    int g = -1;
-    while (tried < 8) {
-      const int x = (xcd + tried) & 7;
-      const int s0 = (int)((int64_t)G * x / 8), s1 = (int)((int64_t)G * (x + 1) / 8);
-      const int t = take_one(&a.info->xq[x], lane);
-      if (s0 + t < s1) {
-        g = s0 + t;
-        break;
-      }
-      ++tried;
-    }
+    int task;
+    const int g = next_unit(a, G, xcd, tried, ticket, waiter, task, lane);
     if (g < 0) break;
+    const bool is_task = task >= 0;
 
     const int gc = a.ginfo[3 * g + 1], gs = a.ginfo[3 * g + 2];
     double blo[3], bhi[3], cen[3];
@@ -106,7 +228,7 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
     }
     double theta = a.theta_group ? (double)a.theta_group[g] : a.par[gs].theta;
     if (!(theta >= 0.0 && theta <= 1.0)) {
-      if (lane == 0) atomicOr(&a.info->err, kErrTheta);
+      if (lane == 0 && !is_task) atomicOr(&a.info->err, kErrTheta);
       theta = (theta > 1.0) ? 1.0 : 0.0;
     }
     // A cell's side is the root side times 2^-level exactly, so l / theta =
@@ -124,18 +246,34 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
     const double near2 = __dmul_rn(hd2, 0.25 * kNearFrac * kNearFrac);
 
     ChunkList F, N;
-    bool fok = true, nok = true, corrupt = false;
-    int sp = 1, nlist = 0;
+    bool fok = true, nok = true, corrupt = false, handed = false;
+    int sp, nlist = 0, key = 0;
     int budget = 4 * nslots + 4;
     double lmass = 0.0;
-    if (lane == 0) stk[0] = make_int2(gs, 1);
+    if (!is_task) {
+      if (lane == 0) stk[0] = make_int2(gs, 1);
+      sp = 1;
+    } else {
+      const WalkTask tk = a.tasks[task];
+      sp = tk.rcount;
+      key = tk.key;
+      if (tk.roff < 0 || tk.rcount < 1 || tk.rcount > kStack || tk.roff + tk.rcount > a.range_cap) {
+        corrupt = true;
+        sp = 0;
+      } else {
+        for (int k = lane; k < sp; k += kWave) stk[k] = a.ranges[tk.roff + k];
+      }
+    }
+    // units at the deepest level walk to the end
+    int cap = (a.visit_cap > 0 && key_depth(key) < kSplitDepth) ? a.visit_cap : 0;
     wave_sync();
+    int visits = 0;
     // Software pipeline: the records of the next batch are loaded while the
     // current batch is tested, so that one batch's memory latency hides
     // behind the other's work.  The next batch is taken from the stack before
     // the current batch pushes its children, except when the stack is high:
     // then the walk is the plain depth-first one of the stack bound above.
-    int bcur = 0;
+    int bcur = 0, ncur = 0;
     NodeRec rcur;
     for (;;) {
       if (--budget < 0) {
@@ -143,7 +281,7 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
         break;
       }
       int bnext = 0, node = 0;
-      const bool starved = sp > kStack - 2 * kWave - kReserve;
+      const bool starved = sp > kStack - 3 * kWave - kReserve;
       if (sp > 0 && (bcur == 0 || !starved)) {
         const int nread = starved ? 1 : min(sp, kWave);
         int2 e = make_int2(0, 0);
@@ -177,6 +315,7 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
       NodeRec rnext;
       if (lane < bnext) rnext = a.nodes[node];
       if (bcur > 0) {
+        visits += bcur;
         bool emit = false, push = false, near = false;
         float4 hi4 = make_float4(0.f, 0.f, 0.f, 0.f), lo4 = hi4;
         int2 rng = make_int2(0, 0);
@@ -246,35 +385,177 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
       wave_sync();
       bcur = bnext;
       rcur = rnext;
+      ncur = node;
       if (bcur == 0 && sp == 0) break;
+      // Visit cap reached: hand the rest (the popped batch as runs of
+      // consecutive nodes, then the stack) to new tasks.
+      if (cap > 0 && visits >= cap) {
+        if (bcur > 0) {
+          const int prev = __shfl_up(ncur, 1, kWave);
+          const bool head = lane < bcur && (lane == 0 || ncur != prev + 1);
+          const unsigned long long hm = __ballot(head);
+          const int runs = __popcll(hm);
+          if (sp + runs > kStack) {
+            corrupt = true;
+            break;
+          }
+          if (head) {
+            // run length: up to the next head (or the end of the batch)
+            const unsigned long long later = hm & ~((2ull << lane) - 1ull);
+            const int end = later ? (__ffsll((long long)later) - 1) : bcur;
+            stk[sp + rank_below(hm)] = make_int2(ncur, end - lane);
+          }
+          sp += runs;
+          bcur = 0;
+          wave_sync();
+        }
+        // The stack's nodes (bottom first) are dealt to the tasks round robin,
+        // one node per range: the ranges at the bottom were pushed first and
+        // hold the largest subtrees, and dealing spreads them over the tasks.
+        int T = 0;
+        for (int k0 = 0; k0 < sp; k0 += kWave) {
+          const int c = (k0 + lane < sp) ? stk[k0 + lane].y : 0;
+          T += __shfl(wave_inclusive_sum(c), kWave - 1, kWave);
+        }
+        T = __builtin_amdgcn_readfirstlane(T);
+        const int nt = min(kDonateTasks, T);
+        // (a task's first stack must leave the room of the stack bound above;
+        // a larger stack, possible only under cells with very many
+        // coincident particles, is walked on by this unit)
+        const bool fits = T <= kDonateTasks * kTaskStack;
+        const int off = __builtin_amdgcn_readfirstlane(atomicAdd(&a.ctr->ranges, (lane == 0 && fits) ? T : 0));
+        const int toff = __builtin_amdgcn_readfirstlane(atomicAdd(&a.ctr->tasks, (lane == 0 && fits) ? nt : 0));
+        if (!fits) {
+          cap = 0;
+        } else if (off + T > a.range_cap || toff + nt > a.task_cap) {
+          // no room: report (the host grows the pools and walks again), walk
+          // on as one unit, and release the reserved slots empty
+          if (lane == 0) atomicOr(&a.info->err, kErrPool);
+          if (lane < nt && toff + lane < a.task_cap)
+            __hip_atomic_store(&a.tasks[toff + lane].rcount, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          cap = 0;
+        } else {
+          // count the new units before any of them can run and finish
+          const int pend = atomicAdd(&a.ctr->pending, lane == 0 ? nt : 0);
+          if (__builtin_amdgcn_readfirstlane(pend) < 0 && lane == 0) atomicOr(&a.info->err, kErrStack);
+          // node q goes to task q % nt, as its (q / nt)-th range; task j's
+          // ranges start at j * (T / nt) + min(j, T % nt)
+          const int per = T / nt, extra = T % nt;
+          int q0 = 0;
+          for (int k0 = 0; k0 < sp; k0 += kWave) {
+            const int2 e = (k0 + lane < sp) ? stk[k0 + lane] : make_int2(0, 0);
+            const int inc = wave_inclusive_sum(e.y);
+            for (int u = 0; u < e.y; ++u) {
+              const int q = q0 + inc - e.y + u, j = q % nt;
+              a.ranges[off + j * per + min(j, extra) + q / nt] = make_int2(e.x + u, 1);
+            }
+            q0 += __shfl(inc, kWave - 1, kWave);
+          }
+          const int cnt = (lane < nt) ? per + (lane < extra ? 1 : 0) : 0;
+          if (lane < nt) {
+            WalkTask *tk = a.tasks + toff + lane;
+            tk->g = g;
+            tk->roff = off + lane * per + min(lane, extra);
+            tk->key = key * (kDonateTasks + 1) + lane + 1;
+          }
+          // publish: every lane's ranges and task fields before any rcount
+          wave_sync();
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          if (lane < nt)
+            __hip_atomic_store(&a.tasks[toff + lane].rcount, cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          handed = true;
+          sp = 0;
+          break;
+        }
+      }
+    }
+    if (!corrupt) {
+#pragma unroll
+      for (int d = 1; d < kWave; d <<= 1) lmass += shfl_xor_d(lmass, d);
+      if (!fok || !nok) {
+        if (lane == 0) atomicOr(&a.info->err, kErrPool);
+      }
     }
     if (corrupt) {
       if (lane == 0) {
         atomicOr(&a.info->err, kErrStack);
-        int32_t *q = a.glists + 4 * (int64_t)g;
-        q[0] = -1;
-        q[1] = 0;
-        q[2] = -1;
-        q[3] = 0;
+        if (!is_task) {
+          int32_t *q = a.glists + 4 * (int64_t)g;
+          q[0] = -1;
+          q[1] = 0;
+          q[2] = -1;
+          q[3] = 0;
+          a.gsplit[g] = 0;
+        }
       }
-      continue;
+    } else if (!is_task && !handed) {
+      if (lane == 0) {
+        int32_t *q = a.glists + 4 * (int64_t)g;
+        q[0] = fok ? F.head : -1;
+        q[1] = F.count;
+        q[2] = nok ? N.head : -1;
+        q[3] = N.count;
+        a.gsplit[g] = 0;
+        a.glist[g] = nlist;
+        a.gmass[g] = lmass;
+        atomicAdd(&a.info->interactions, (unsigned long long)gc * (unsigned long long)(nlist - 1));
+        atomicAdd(&a.info->list_entries, (unsigned long long)nlist);
+        atomicMax(&a.info->max_list, nlist);
+      }
+    } else {
+      // a segment of a split group: its list so far; totals come later
+      const int sidx = __builtin_amdgcn_readfirstlane(atomicAdd(&a.ctr->segs, lane == 0 ? 1 : 0));
+      if (lane == 0) {
+        if (!is_task) {
+          int32_t *q = a.glists + 4 * (int64_t)g;
+          q[0] = -1;
+          q[1] = 0;
+          q[2] = -1;
+          q[3] = 0;
+          a.gsplit[g] = 1;
+          atomicAdd(&a.ctr->n_split, 1);
+        }
+        atomicMax(&a.ctr->depth, key_depth(key) + (handed ? 1 : 0));
+        if (sidx < a.seg_cap) {
+          Segment sg;
+          sg.g = g;
+          sg.key = key;
+          sg.fh = fok ? F.head : -1;
+          sg.fn = F.count;
+          sg.nh = nok ? N.head : -1;
+          sg.nn = N.count;
+          sg.len = nlist;
+          sg.pad = 0;
+          sg.mass = lmass;
+          a.segs[sidx] = sg;
+        } else {
+          atomicOr(&a.info->err, kErrPool);
+        }
+      }
     }
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) lmass += shfl_xor_d(lmass, d);
-    if (lane == 0) {
-      int32_t *q = a.glists + 4 * (int64_t)g;
-      q[0] = fok ? F.head : -1;
-      q[1] = F.count;
-      q[2] = nok ? N.head : -1;
-      q[3] = N.count;
-      if (!fok || !nok) atomicOr(&a.info->err, kErrPool);
-      a.glist[g] = nlist;
-      a.gmass[g] = lmass;
-      atomicAdd(&a.info->interactions, (unsigned long long)gc * (unsigned long long)(nlist - 1));
-      atomicAdd(&a.info->list_entries, (unsigned long long)nlist);
-      atomicMax(&a.info->max_list, nlist);
+    // this unit is done; a unit that published tasks orders them before
+    // its decrement (the others published nothing that waiters read)
+    if (a.visit_cap > 0) {
+      if (handed) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      atomicAdd(&a.ctr->pending, lane == 0 ? -1 : 0);
     }
   }
+}
+
+// Counters of the split walk, and every task slot unpublished (rcount -1).
+__global__ void k_split_reset(SplitCounters *ctr, const DevInfo *info, WalkTask *tasks, int task_cap) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    ctr->tasks = 0;
+    ctr->queue = 0;
+    ctr->ranges = 0;
+    ctr->segs = 0;
+    ctr->n_split = 0;
+    ctr->pending = info->n_groups;
+    ctr->depth = 0;
+    ctr->waiters = 0;
+  }
+  if (i < task_cap) tasks[i].rcount = -1;
 }
 
 __global__ void k_reset_queue(DevInfo *info) { info->queue = 0; }
@@ -441,6 +722,10 @@ int walk_lists_blocks_per_cu() {
 
 void walk_lists_device(const WalkListArgs &a, int grid, hipStream_t s) {
   k_walk_lists<<<(unsigned)grid, kWave, 0, s>>>(a);
+}
+
+void split_reset(SplitCounters *ctr, const DevInfo *info, WalkTask *tasks, int task_cap, hipStream_t s) {
+  k_split_reset<<<(unsigned)((task_cap + 255) / 256), 256, 0, s>>>(ctr, info, tasks, task_cap);
 }
 
 int probe_blocks_per_cu() {
