@@ -41,10 +41,10 @@ FLOPS_PER_INTERACTION = 20      # 3 sub, 3 FMA (r^2), rsqrt, 3 mul, 3 FMA (acc),
 # device copy of known size), valid only for the kernel source it was taken on.
 TRAFFIC = {
     # clustered box, 2,097,152 particles, theta 0.4203125 (the 1e-3 RMS theta):
-    # FETCH_SIZE 3004309.5 KiB x 1.99987 (a 512 MiB device copy reads as
-    # 262160.5 KiB) + WRITE_SIZE 146230.0 KiB x 1.0 (the copy writes 524288 KiB)
-    "clustered_2m": {"theta": 0.4203125, "bytes_per_launch": 6302178051,
-                     "k_force_sha256": "dd0ee55e76c7b3e173907dd2b938265a5efbac74df126f8a7707be92d3e476fb"},
+    # FETCH_SIZE 2955915.6 KiB x 1.99987 (a 512 MiB device copy reads as
+    # 262160.5 KiB) + WRITE_SIZE 155064.0 KiB x 1.0 (the copy writes 524288 KiB)
+    "clustered_2m": {"theta": 0.4203125, "bytes_per_launch": 6212119596,
+                     "k_force_sha256": "bf6931e36079adee4481c5dd1a9b81c63315b8e9e226d9bfd08e64ce75ec68fa"},
 }
 
 
