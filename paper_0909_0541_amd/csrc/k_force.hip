@@ -1,9 +1,10 @@
 // Force sum over the interaction lists (Eq. 1, FP32 with group-relative
 // coordinates, partial sums folded into FP64).
 //
-// Work items are (group, block of at most 64 members); a persistent grid of
-// single-wave workgroups pulls items from an atomic queue.  A block of m
-// members uses R lane partitions of W = 64/R >= m lanes, one member per lane;
+// Work items are (group, block of 64 members, or the group's remainder); a
+// persistent grid of single-wave workgroups pulls items from an atomic queue.
+// A block of m members uses R lane partitions of W = 64/R >= m lanes, one
+// member per lane;
 // partition `part` takes list entries part, part + R, ...  With R = 1 every
 // lane reads the same entry, so entries are fetched with scalar loads and used
 // as scalar operands.  Per term a lane computes dx = x_j - x_i (near entries:
@@ -79,6 +80,31 @@ __device__ __forceinline__ void fold(Member &M) {
 
 constexpr int kU = 8;  // entries per block of terms
 
+// One chunk with R lane partitions: partition `part` takes entries part,
+// part + R, ...; R is a compile-time constant so that the four entries of a
+// block are loaded at constant offsets from one running pointer.
+template <bool NEAR, int R>
+__device__ __forceinline__ void chunk_part(Member &M, const float4 *__restrict__ h, const float4 *__restrict__ l,
+                                           int n, int part, float eps2) {
+  const int mine = (n - part + R - 1) / R;
+  const float4 *ph = h + part;
+  const float4 *pl = l + part;
+  int t = 0;
+  for (; t + 4 <= mine; t += 4, ph += 4 * R, pl += 4 * R) {
+    float4 e4[4], r4[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      e4[u] = ph[u * R];
+      r4[u] = NEAR ? pl[u * R] : e4[u];
+    }
+    terms<4, NEAR>(M, e4, r4, eps2);
+  }
+  for (; t < mine; ++t, ph += R, pl += R) {
+    const float4 e1[1] = {ph[0]}, r1[1] = {NEAR ? pl[0] : ph[0]};
+    terms<1, NEAR>(M, e1, r1, eps2);
+  }
+}
+
 // n entries of one chunk: values at h[0..n), residues at l[0..n) when NEAR.
 template <bool NEAR>
 __device__ __forceinline__ void chunk_sum(Member &M, const float4 *__restrict__ h, const float4 *__restrict__ l,
@@ -115,21 +141,13 @@ __device__ __forceinline__ void chunk_sum(Member &M, const float4 *__restrict__ 
       terms<1, NEAR>(M, e1, r1, eps2);
     }
   } else {
-    // partition `part` takes entries part, part + R, ...
-    const int mine = (n - part + R - 1) / R;
-    int t = 0;
-    for (; t + 4 <= mine; t += 4) {
-      float4 e4[4], r4[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        e4[u] = h[(t + u) * R + part];
-        r4[u] = NEAR ? l[(t + u) * R + part] : e4[u];
-      }
-      terms<4, NEAR>(M, e4, r4, eps2);
-    }
-    for (; t < mine; ++t) {
-      const float4 e1[1] = {h[t * R + part]}, r1[1] = {NEAR ? l[t * R + part] : h[t * R + part]};
-      terms<1, NEAR>(M, e1, r1, eps2);
+    switch (R) {
+      case 2: chunk_part<NEAR, 2>(M, h, l, n, part, eps2); break;
+      case 4: chunk_part<NEAR, 4>(M, h, l, n, part, eps2); break;
+      case 8: chunk_part<NEAR, 8>(M, h, l, n, part, eps2); break;
+      case 16: chunk_part<NEAR, 16>(M, h, l, n, part, eps2); break;
+      case 32: chunk_part<NEAR, 32>(M, h, l, n, part, eps2); break;
+      default: chunk_part<NEAR, 64>(M, h, l, n, part, eps2); break;
     }
   }
   fold(M);
@@ -169,9 +187,9 @@ __global__ __launch_bounds__(kWave) void k_force_lists(ForceArgs a, const float4
       prow = a.pbase[p];
     }
     if ((fn > 0 && fh < 0) || (nn > 0 && nh < 0)) continue;  // incomplete list (reported by the walk)
-    // members [b0, b1) of the group: blocks of near-equal size, at most 64
-    const int nb = (gc + kWave - 1) / kWave;
-    const int b0 = (int)((int64_t)gc * blk / nb), b1 = (int)((int64_t)gc * (blk + 1) / nb);
+    // members [b0, b1) of the group: full blocks of 64, then the remainder,
+    // which takes several lane partitions when it is small
+    const int b0 = blk * kWave, b1 = min(gc, b0 + kWave);
     const int m = b1 - b0;
     int R = 1;
     while (R < kWave && m * (2 * R) <= kWave) R *= 2;

@@ -24,8 +24,7 @@ __device__ __forceinline__ int item_key(const ForceArgs &f, int64_t it) {
   const int g = f.items[2 * it], iv = f.items[2 * it + 1];
   const int blk = iv & 255, segl = iv >> 8;
   const int gc = f.ginfo[3 * g + 1];
-  const int nb = (gc + kWave - 1) / kWave;
-  const int m = (int)((int64_t)gc * (blk + 1) / nb) - (int)((int64_t)gc * blk / nb);
+  const int m = min(gc - blk * kWave, kWave);  // full blocks of 64, then the remainder
   int R = 1;
   while (R < kWave && m * (2 * R) <= kWave) R *= 2;
   int64_t len;
