@@ -601,8 +601,9 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
     c->last_depth = visit_cap > 0 ? c->split_host->depth : 0;
     if (!(c->info_host->err & kErrPool)) break;
     if (attempt > 5) return fail(c, BH_EINTERNAL, "interaction list pool still too small after growing");
-    c->far_cap = std::max(c->far_cap, (int32_t)(c->info_host->far_chunks + c->info_host->far_chunks / 4 + 64));
-    c->near_cap = std::max(c->near_cap, (int32_t)(c->info_host->near_chunks + c->info_host->near_chunks / 4 + 64));
+    const int64_t fneed = (int64_t)c->info_host->far_chunks * kChunkRun, nneed = (int64_t)c->info_host->near_chunks * kChunkRun;
+    c->far_cap = std::max(c->far_cap, (int32_t)std::min<int64_t>(fneed + fneed / 4 + 64, INT32_MAX / 2));
+    c->near_cap = std::max(c->near_cap, (int32_t)std::min<int64_t>(nneed + nneed / 4 + 64, INT32_MAX / 2));
     if (visit_cap > 0) {
       const SplitCounters &h = *c->split_host;
       if (h.tasks > c->task_cap) c->task_cap = std::max(2 * c->task_cap, h.tasks + h.tasks / 4 + 64);

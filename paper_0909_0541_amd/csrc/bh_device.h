@@ -27,25 +27,33 @@ __device__ __forceinline__ int rank_below(unsigned long long m) {
   return (int)__popcll(m & __lanemask_lt());
 }
 
-// Inclusive prefix sum over the 64 lanes of a wave.
+// Inclusive prefix sum and maximum over the 64 lanes of a wave, in data-
+// parallel-primitive (DPP) moves between lanes instead of LDS permutes:
+// shifts by 1, 2, 4 and 8 lanes within each row of 16 (a Hillis-Steele scan
+// of the row), then row 15's last lane broadcast into rows 1 and 3 and lane
+// 31 into rows 2 and 3.  Lanes whose source lies outside the row take the
+// identity.  Call with all lanes active.
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143;
+
 __device__ __forceinline__ int wave_inclusive_sum(int v) {
-  const int l = lane_id();
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    int t = __shfl_up(v, d, kWave);
-    if (l >= d) v += t;
-  }
+  v += __builtin_amdgcn_update_dpp(0, v, kDppRowShr1, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, kDppRowShr2, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, kDppRowShr4, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, kDppRowShr8, 0xf, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, kDppRowBcast15, 0xa, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, kDppRowBcast31, 0xc, 0xf, false);
   return v;
 }
 
-// Inclusive prefix maximum over the 64 lanes of a wave.
 __device__ __forceinline__ int wave_inclusive_max(int v) {
-  const int l = lane_id();
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    int t = __shfl_up(v, d, kWave);
-    if (l >= d) v = max(v, t);
-  }
+  constexpr int kId = -2147483647 - 1;
+  v = max(v, __builtin_amdgcn_update_dpp(kId, v, kDppRowShr1, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(kId, v, kDppRowShr2, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(kId, v, kDppRowShr4, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(kId, v, kDppRowShr8, 0xf, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(kId, v, kDppRowBcast15, 0xa, 0xf, false));
+  v = max(v, __builtin_amdgcn_update_dpp(kId, v, kDppRowBcast31, 0xc, 0xf, false));
   return v;
 }
 

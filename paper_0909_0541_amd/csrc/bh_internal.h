@@ -60,7 +60,7 @@ struct DevInfo {
   unsigned long long list_entries;
   int32_t max_list;
   int32_t queue2;         // force work queue head
-  int32_t far_chunks;     // list chunks taken (may exceed the pool: then it is the need)
+  int32_t far_chunks;     // runs of kChunkRun list chunks taken (may exceed the pool: then it is the need)
   int32_t near_chunks;
   int32_t n_items;        // force work items (group, member block)
   int32_t pad2;
@@ -72,6 +72,7 @@ struct DevInfo {
 // float4 rounding residues), 8 KiB each.
 constexpr int kFarChunk = 512;
 constexpr int kNearChunk = 256;
+constexpr int kChunkRun = 4;    // chunks a walk wave takes from a pool per atomic
 // Near entries: within kNearFrac times the box half-diagonal of the box.
 constexpr double kNearFrac = 0.1;
 

@@ -55,12 +55,35 @@ struct ChunkList {
   int cap = 0;     // entries that fit in the chunks taken so far
 };
 
+// The list chunks of one wave: taken from the pool kChunkRun at a time (one
+// atomic on the shared counter per run) and handed out in order; the rest of a
+// run carries over from unit to unit.  The next run is requested while the
+// list is within two batches of needing a chunk and the current run is used
+// up, together with a batch's node loads, and its number is read at the top
+// of the next iteration, so the atomic's round trip overlaps a batch.
+struct ChunkSource {
+  int next = 0, end = 0;  // chunks [next, end) of the current run
+  int spare = -1;         // a run that has arrived
+  int req = 0;            // a requested run (VGPR, read once arrived)
+  bool pend = false;
+};
+
+__device__ __forceinline__ int take_chunk(ChunkSource &S, int *counter, int lane) {
+  if (S.next >= S.end) {
+    const int run = (S.spare >= 0) ? S.spare : take_one(counter, lane);
+    S.spare = -1;
+    S.next = run * kChunkRun;
+    S.end = S.next + kChunkRun;
+  }
+  return S.next++;
+}
+
 // Make room for n more entries (n <= chunk size); returns false when the pool
 // is exhausted (the list is then incomplete but keeps being counted).
-__device__ __forceinline__ bool reserve(ChunkList &L, int n, int chunk, int *counter, int pool_chunks,
-                                        int32_t *__restrict__ next, int lane, bool ok) {
+__device__ __forceinline__ bool reserve(ChunkList &L, int n, int chunk, ChunkSource &S, int *counter,
+                                        int pool_chunks, int32_t *__restrict__ next, int lane, bool ok) {
   if (L.count + n <= L.cap) return ok;
-  const int c = take_one(counter, lane);
+  const int c = take_chunk(S, counter, lane);
   L.cap += chunk;
   if (!ok || c >= pool_chunks) return false;
   if (L.cur >= 0) {
@@ -212,6 +235,7 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
   const int xcd = blockIdx.x & 7;
   int tried = 0, ticket = -1;
   bool waiter = false;
+  ChunkSource fsrc, nsrc;  // this wave's far and near list chunks
   for (;;) {
     int task;
     const int g = next_unit(a, G, xcd, tried, ticket, waiter, task, lane);
@@ -280,6 +304,14 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
         corrupt = true;
         break;
       }
+      if (fsrc.pend) {
+        fsrc.spare = __builtin_amdgcn_readfirstlane(fsrc.req);
+        fsrc.pend = false;
+      }
+      if (nsrc.pend) {
+        nsrc.spare = __builtin_amdgcn_readfirstlane(nsrc.req);
+        nsrc.pend = false;
+      }
       int bnext = 0, node = 0;
       const bool starved = sp > kStack - 3 * kWave - kReserve;
       if (sp > 0 && (bcur == 0 || !starved)) {
@@ -314,6 +346,14 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
       }
       NodeRec rnext;
       if (lane < bnext) rnext = a.nodes[node];
+      if (fsrc.spare < 0 && fsrc.next >= fsrc.end && F.cap - F.count < 2 * kWave) {
+        fsrc.req = atomicAdd(&a.info->far_chunks, lane == 0 ? 1 : 0);
+        fsrc.pend = true;
+      }
+      if (nsrc.spare < 0 && nsrc.next >= nsrc.end && N.cap - N.count < 2 * kWave) {
+        nsrc.req = atomicAdd(&a.info->near_chunks, lane == 0 ? 1 : 0);
+        nsrc.pend = true;
+      }
       if (bcur > 0) {
         visits += bcur;
         bool emit = false, push = false, near = false;
@@ -362,7 +402,7 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
         if (push) stk[sp + rank_below(pm)] = rng;
         const int nf = __popcll(fm), nn = __popcll(nm);
         if (nf > 0) {
-          fok = reserve(F, nf, kFarChunk, &a.info->far_chunks, a.far_cap, a.far_next, lane, fok);
+          fok = reserve(F, nf, kFarChunk, fsrc, &a.info->far_chunks, a.far_cap, a.far_next, lane, fok);
           if (fok && emit && !near) {
             const int pos = F.count + rank_below(fm);
             a.far_pool[(int64_t)chunk_of(F, pos, kFarChunk) * kFarChunk + pos % kFarChunk] = hi4;
@@ -370,7 +410,7 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
           F.count += nf;
         }
         if (nn > 0) {
-          nok = reserve(N, nn, kNearChunk, &a.info->near_chunks, a.near_cap, a.near_next, lane, nok);
+          nok = reserve(N, nn, kNearChunk, nsrc, &a.info->near_chunks, a.near_cap, a.near_next, lane, nok);
           if (nok && emit && near) {
             const int pos = N.count + rank_below(nm);
             float4 *base = a.near_pool + (int64_t)chunk_of(N, pos, kNearChunk) * (2 * kNearChunk);
