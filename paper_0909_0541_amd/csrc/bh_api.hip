@@ -646,8 +646,8 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
   if (st) return st;
   st = ensure(c, c->item_order, sizeof(int32_t) * icap, "force order");
   if (st) return st;
-  force_items_device(P<int32_t>(c->ginfo), P<int32_t>(c->gsplit), P<int32_t>(c->gnseg), P<DevInfo>(c->info),
-                     (int64_t)gcap, P<int32_t>(c->item_n), P<int32_t>(c->item_off), P<int32_t>(c->items),
+  force_items_device(P<int32_t>(c->ginfo), P<int32_t>(c->gsplit), P<int32_t>(c->gnseg), P<int32_t>(c->glist),
+                     P<DevInfo>(c->info), (int64_t)gcap, P<int32_t>(c->item_n), P<int32_t>(c->item_off), P<int32_t>(c->items),
                      c->scan_tmp.p, c->stream);
   ForceArgs F{};
   F.items = P<int32_t>(c->items);

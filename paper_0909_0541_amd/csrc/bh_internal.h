@@ -48,6 +48,8 @@ struct SysParam {
   double theta;
 };
 
+constexpr int kLineInts = 32;  // int32 per 128-byte line
+
 // Device-side counters and flags (one instance per context).
 struct DevInfo {
   int32_t err;            // error flag bits (kErr*)
@@ -59,12 +61,13 @@ struct DevInfo {
   unsigned long long interactions;
   unsigned long long list_entries;
   int32_t max_list;
-  int32_t queue2;         // force work queue head
-  int32_t far_chunks;     // runs of kChunkRun list chunks taken (may exceed the pool: then it is the need)
-  int32_t near_chunks;
   int32_t n_items;        // force work items (group, member block)
-  int32_t pad2;
-  int32_t xq[8];          // walk queue heads, one per XCD
+  // Counters that every wave of a kernel updates, each in a 128-byte line of
+  // its own (atomics on one line serialise behind each other).
+  alignas(128) int32_t queue2;  // force work queue head
+  alignas(128) int32_t far_chunks;   // runs of kChunkRun list chunks taken (may exceed the pool: then it is the need)
+  alignas(128) int32_t near_chunks;
+  alignas(128) int32_t xq[8 * kLineInts];  // walk queue heads, one per XCD: xq[x * kLineInts]
 };
 
 // Interaction lists: chunks of kFarChunk far entries (float4 x - c_g, m) and
@@ -390,8 +393,9 @@ struct ForceArgs {
   const int32_t *pbase;       // sorted position -> first partial-sum row
   double *psum;               // [rows][4] ax, ay, az, pot
 };
-void force_items_device(const int32_t *ginfo, const int32_t *gsplit, const int32_t *gnseg, DevInfo *info, int64_t cap,
-                        int32_t *nblk, int32_t *off, int32_t *items, void *scan_tmp, hipStream_t s);
+void force_items_device(const int32_t *ginfo, const int32_t *gsplit, const int32_t *gnseg, const int32_t *glist,
+                        DevInfo *info, int64_t cap, int32_t *nblk, int32_t *off, int32_t *items, void *scan_tmp,
+                        hipStream_t s);
 void force_lists_device(const ForceArgs &a, int grid, hipStream_t s);
 void item_order_device(const ForceArgs &f, int64_t cap, int32_t *hist, int32_t *order, hipStream_t s);
 int force_lists_blocks_per_cu();

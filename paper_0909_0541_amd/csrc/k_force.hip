@@ -268,18 +268,42 @@ __global__ __launch_bounds__(kWave) void k_force_lists(ForceArgs a, const float4
   }
 }
 
-// Member blocks per group (ceil(count / 64)), times the segments of a split group.
-__global__ void k_item_counts(const int32_t *__restrict__ ginfo, const int32_t *__restrict__ gsplit,
-                              const int32_t *__restrict__ gnseg, const DevInfo *__restrict__ info, int64_t cap,
-                              int32_t *__restrict__ nblk) {
+// Member blocks per group (ceil(count / 64)), times the segments of a split
+// group; and the list statistics (interactions, entries, longest list), one
+// atomic per wave rather than per group.
+__global__ __launch_bounds__(256) void k_item_counts(const int32_t *__restrict__ ginfo,
+                                                     const int32_t *__restrict__ gsplit,
+                                                     const int32_t *__restrict__ gnseg,
+                                                     const int32_t *__restrict__ glist, DevInfo *__restrict__ info,
+                                                     int64_t cap, int32_t *__restrict__ nblk) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= cap) return;
+  const int G = info->n_groups;
+  if ((int64_t)blockIdx.x * blockDim.x >= cap) return;  // whole block
   int nb = 0;
-  if (g < info->n_groups) {
-    nb = (ginfo[3 * g + 1] + kWave - 1) / kWave;
+  unsigned long long inter = 0, entries = 0;
+  int longest = 0;
+  if (g < G) {
+    const int c = ginfo[3 * g + 1];
+    nb = (c + kWave - 1) / kWave;
     if (gsplit[g]) nb *= gnseg[g];
+    const int len = glist[g];
+    inter = (unsigned long long)c * (unsigned long long)max(len - 1, 0);
+    entries = (unsigned long long)len;
+    longest = len;
   }
-  nblk[g] = nb;
+  if (g < cap) nblk[g] = nb;
+  if ((int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)) >= G) return;  // whole wave past the groups
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    inter += __shfl_xor(inter, d, kWave);
+    entries += __shfl_xor(entries, d, kWave);
+    longest = max(longest, __shfl_xor(longest, d, kWave));
+  }
+  if (lane_id() == 0) {
+    atomicAdd(&info->interactions, inter);
+    atomicAdd(&info->list_entries, entries);
+    atomicMax(&info->max_list, longest);
+  }
 }
 
 // Items as (group, member block + 256 x (segment + 1) for a split group).
@@ -300,10 +324,11 @@ __global__ void k_item_fill(const int32_t *__restrict__ ginfo, const int32_t *__
 
 }  // namespace
 
-void force_items_device(const int32_t *ginfo, const int32_t *gsplit, const int32_t *gnseg, DevInfo *info, int64_t cap,
-                        int32_t *nblk, int32_t *off, int32_t *items, void *scan_tmp, hipStream_t s) {
+void force_items_device(const int32_t *ginfo, const int32_t *gsplit, const int32_t *gnseg, const int32_t *glist,
+                        DevInfo *info, int64_t cap, int32_t *nblk, int32_t *off, int32_t *items, void *scan_tmp,
+                        hipStream_t s) {
   const unsigned blocks = (unsigned)((cap + 255) / 256);
-  k_item_counts<<<blocks, 256, 0, s>>>(ginfo, gsplit, gnseg, info, cap, nblk);
+  k_item_counts<<<blocks, 256, 0, s>>>(ginfo, gsplit, gnseg, glist, info, cap, nblk);
   scan_exclusive_i32(nblk, off, cap, &info->n_items, scan_tmp, s);
   k_item_fill<<<blocks, 256, 0, s>>>(ginfo, gsplit, gnseg, off, info, items);
 }

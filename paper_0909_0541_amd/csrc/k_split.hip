@@ -91,9 +91,6 @@ __global__ void k_seg_finish(const Segment *__restrict__ segs, const uint32_t *_
   glist[g] = len;
   gmass[g] = mass;
   sgroups[atomicAdd(nsg, 1)] = g;
-  atomicAdd(&info->interactions, (unsigned long long)c * (unsigned long long)(len - 1));
-  atomicAdd(&info->list_entries, (unsigned long long)len);
-  atomicMax(&info->max_list, len);
 }
 
 // One block per split group, one thread per member.

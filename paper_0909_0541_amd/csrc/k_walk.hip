@@ -172,7 +172,7 @@ __device__ __forceinline__ int next_unit(const WalkListArgs &a, int G, int xcd, 
       while (tried < 8) {
         const int x = __builtin_amdgcn_readfirstlane((xcd + tried) & 7);
         const int s0 = (int)((int64_t)G * x / 8), s1 = (int)((int64_t)G * (x + 1) / 8);
-        const int q = take_one(&a.info->xq[x], lane);
+        const int q = take_one(&a.info->xq[x * kLineInts], lane);
         if (s0 + q < s1) {
           g = s0 + q;
           break;
@@ -526,6 +526,7 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
           q[2] = -1;
           q[3] = 0;
           a.gsplit[g] = 0;
+          a.glist[g] = 0;
         }
       }
     } else if (!is_task && !handed) {
@@ -536,11 +537,8 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
         q[2] = nok ? N.head : -1;
         q[3] = N.count;
         a.gsplit[g] = 0;
-        a.glist[g] = nlist;
+        a.glist[g] = nlist;  // statistics are summed from these after the walk
         a.gmass[g] = lmass;
-        atomicAdd(&a.info->interactions, (unsigned long long)gc * (unsigned long long)(nlist - 1));
-        atomicAdd(&a.info->list_entries, (unsigned long long)nlist);
-        atomicMax(&a.info->max_list, nlist);
       }
     } else {
       // a segment of a split group: its list so far; totals come later
