@@ -41,10 +41,10 @@ FLOPS_PER_INTERACTION = 20      # 3 sub, 3 FMA (r^2), rsqrt, 3 mul, 3 FMA (acc),
 # device copy of known size), valid only for the kernel source it was taken on.
 TRAFFIC = {
     # clustered box, 2,097,152 particles, theta 0.4203125 (the 1e-3 RMS theta):
-    # FETCH_SIZE 2955915.6 KiB x 1.99987 (a 512 MiB device copy reads as
-    # 262160.5 KiB) + WRITE_SIZE 155064.0 KiB x 1.0 (the copy writes 524288 KiB)
-    "clustered_2m": {"theta": 0.4203125, "bytes_per_launch": 6212119596,
-                     "k_force_sha256": "bf6931e36079adee4481c5dd1a9b81c63315b8e9e226d9bfd08e64ce75ec68fa"},
+    # FETCH_SIZE 2852897.1 KiB x 1.99987 (a 512 MiB device copy reads as
+    # 262160.75 KiB) + WRITE_SIZE 155006.9 KiB x 1.0 (the copy writes 524288 KiB)
+    "clustered_2m": {"theta": 0.4203125, "bytes_per_launch": 6001086952,
+                     "k_force_sha256": "2be925f64e4395089096f444cb0d9b5934bb8f5f1bf0917d7e37cd740c71e977"},
 }
 
 
