@@ -12,11 +12,11 @@ namespace bh {
 
 namespace {
 
+// Zero every word of the counters (one block; the struct is a few lines).
 __global__ void k_reset_info(DevInfo *info) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    DevInfo z{};
-    *info = z;
-  }
+  static_assert(sizeof(DevInfo) % sizeof(int32_t) == 0, "DevInfo is a whole number of words");
+  int32_t *w = reinterpret_cast<int32_t *>(info);
+  for (int i = threadIdx.x; i < (int)(sizeof(DevInfo) / sizeof(int32_t)); i += blockDim.x) w[i] = 0;
 }
 
 __global__ void k_export_nodes(const NodeRec *__restrict__ nodes, const int8_t *__restrict__ meta,
@@ -82,7 +82,7 @@ inline unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)((n + t - 
 
 }  // namespace
 
-void reset_info_device(DevInfo *info, hipStream_t s) { k_reset_info<<<1, 64, 0, s>>>(info); }
+void reset_info_device(DevInfo *info, hipStream_t s) { k_reset_info<<<1, 256, 0, s>>>(info); }
 
 bh_status fail(bh_ctx *c, bh_status st, const std::string &msg) {
   if (c) c->err = msg;
