@@ -97,8 +97,9 @@ typedef struct {
                             stack to up to 16 new walk tasks, which waves with no group left
                             take in the same launch, so that long lists are walked and summed
                             by several waves; tasks 5 hand-overs deep walk to the end (0:
-                            default 12288; -1: never; else >= 64).  Results do not depend on
-                            when or where the tasks ran, only on this value. */
+                            default, 18 per particle of a walk wave, i.e. 18 n / (CUs x walk
+                            waves per CU), at least 12288; -1: never; else >= 64).  Results
+                            do not depend on when or where the tasks ran, only on the cap. */
 } bh_options;
 
 /* ---- context ---------------------------------------------------------- */
@@ -177,7 +178,10 @@ bh_status bh_make_groups(bh_ctx *ctx, int32_t n_crit, int64_t *n_groups_out);
 bh_status bh_compute_forces(bh_ctx *ctx, double eps, double theta, const float *theta_group, float *acc,
                             float *pot);
 
-/* Same with per-system parameters: eps_sys, theta_sys host FP64 [n_systems]. */
+/* Same with per-system parameters: eps_sys, theta_sys host FP64 [n_systems].
+ * A system's results equal, bit for bit, those of the same system run alone
+ * with the same split-walk visit cap (the default cap grows with the total
+ * particle count, so set bh_options.split_visits explicitly for that). */
 bh_status bh_compute_forces_batch(bh_ctx *ctx, const double *eps_sys, const double *theta_sys,
                                   const float *theta_group, float *acc, float *pot);
 

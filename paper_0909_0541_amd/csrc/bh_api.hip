@@ -519,7 +519,16 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
   }
   const size_t gcap = (size_t)std::max<int64_t>(c->n, 1);
   // split walks (long lists walked and summed by several waves)
-  const int visit_cap = c->opt.split_visits < 0 ? 0 : (c->opt.split_visits == 0 ? kSplitVisits : c->opt.split_visits);
+  const int grid = c->num_cu * (c->opt.waves_per_cu > 0 ? c->opt.waves_per_cu : c->walk_bpc);
+  const int fgrid = c->num_cu * (c->opt.waves_per_cu > 0 ? c->opt.waves_per_cu : c->force_bpc);
+  // The default visit cap scales with the particles per walk wave (a walk
+  // that outlasts the average wave's share of the walk is the one to split;
+  // that share grows with the particles per wave), never below kSplitVisits.
+  const int64_t auto_cap = std::max<int64_t>(kSplitVisits, kSplitPerParticle * c->n / std::max(grid, 1));
+  const int visit_cap = c->opt.split_visits < 0
+                            ? 0
+                            : (c->opt.split_visits == 0 ? (int)std::min<int64_t>(auto_cap, INT32_MAX / 2)
+                                                        : c->opt.split_visits);
   if (c->seg_cap == 0) {
     c->task_cap = 4096;
     c->range_cap = 1 << 16;
@@ -527,8 +536,6 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
   }
   st = ensure(c, c->order_hist, order_hist_bytes(), "queue order bins");
   if (st) return st;
-  const int grid = c->num_cu * (c->opt.waves_per_cu > 0 ? c->opt.waves_per_cu : c->walk_bpc);
-  const int fgrid = c->num_cu * (c->opt.waves_per_cu > 0 ? c->opt.waves_per_cu : c->force_bpc);
   SplitBuffers S{};
   int32_t nsegs_host = 0;
   for (int attempt = 0;; ++attempt) {

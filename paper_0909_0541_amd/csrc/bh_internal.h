@@ -109,7 +109,8 @@ struct Segment {
   double mass;
 };
 constexpr int kSplitDepth = 5;       // tasks this many hand-overs deep walk to the end
-constexpr int kSplitVisits = 12288;  // default node tests before a walk hands over
+constexpr int kSplitVisits = 12288;  // smallest default node tests before a walk hands over
+constexpr int kSplitPerParticle = 18;  // default cap: this many node tests per particle of a walk wave
 constexpr int kDonateTasks = 16;     // tasks made from one handed-over stack
 struct SplitCounters {               // device
   int32_t tasks;                     // task slots reserved

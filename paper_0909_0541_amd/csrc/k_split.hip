@@ -31,7 +31,7 @@ __global__ void k_seg_keys(const Segment *__restrict__ segs, const SplitCounters
 // against 256-key tiles of the others (a 2-D grid) add to the ranks, then
 // the positions are written; for the thousands of segments of a step this
 // is far cheaper than a radix sort's passes.
-constexpr int kRankSortMax = 65536;
+constexpr int kRankSortMax = 16384;
 constexpr int kRankTile = 256;
 __global__ __launch_bounds__(256) void k_seg_rank(const uint64_t *__restrict__ keys,
                                                   const SplitCounters *__restrict__ ctr, int cap,

@@ -32,8 +32,14 @@ def _small_batch(seed=7):
     return np.concatenate(pos), np.concatenate(mass), off, np.array(eps), np.array(theta)
 
 
+# The default visit cap of split walks grows with the total particle count;
+# a batch and its systems run alone split their walks alike, and so agree bit
+# for bit, when they use the same cap.
+CAP = 12288
+
+
 def _standalone(bh, p, m, eps, theta, n_crit):
-    c = bh.Context()
+    c = bh.Context(split_visits=CAP)
     c.build_tree(to_dev(p), to_dev(m))
     c.make_groups(n_crit)
     a, u = c.compute_forces(eps, theta)
@@ -44,7 +50,7 @@ def _standalone(bh, p, m, eps, theta, n_crit):
 def test_batch_equals_standalone_and_oracle(gpu, n_crit):
     bh = gpu
     pos, mass, off, eps, theta = _small_batch()
-    c = bh.Context()
+    c = bh.Context(split_visits=CAP)
     c.build_batch(off, to_dev(pos), to_dev(mass))
     G = c.make_groups(n_crit)
     acc, pot = c.compute_forces_batch(eps, theta)
@@ -78,7 +84,7 @@ def test_batch_workload_sampled_against_standalone(gpu):
     pos, mass, off, eps = inputs.batch_systems()
     theta = np.full(len(eps), 0.7)
     n_crit = 64
-    c = bh.Context()
+    c = bh.Context(split_visits=CAP)
     c.build_batch(off, to_dev(pos), to_dev(mass))
     c.make_groups(n_crit)
     acc, pot = c.compute_forces_batch(eps, theta)
