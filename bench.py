@@ -207,10 +207,28 @@ def main():
         return {"build": per(st.t_build_ms, st.n_build_calls), "groups": per(st.t_groups_ms, st.n_groups_calls),
                 "walk": per(st.t_walk_ms, st.n_walk_calls), "force": per(st.t_force_ms, st.n_force_calls)}
 
-    ms_per_step, st = learned.timed_steps(fixed, args.steps, args.warmup, theta=theta)
+    ms_eager, st = learned.timed_steps(fixed, args.steps, args.warmup, theta=theta)
     stage = stages(st)
     rms = judge.rms(fixed.acc)
     inter = st.interactions
+    # The timed step: the same whole step (build, groups, list walk, force
+    # sum) captured once as a HIP graph and replayed, which takes the host's
+    # launch work and the force call's list-pool check off the GPU's path.
+    # (A replay that does not reproduce the eager step's forces bit for bit
+    # is not reported: the eager time is then the step time.)
+    from paper_0909_0541_amd import autotune
+    step_mode, graph_error = "graph", None
+    try:
+        gctx = bh.Context(waves_per_cu=args.waves_per_cu)
+        gctx.graph_capture(np.array([0, n], dtype=np.int64), dpos, dmass, w.n_crit, [w.eps], [theta])
+        ms_per_step = autotune.time_graph(gctx, args.steps, args.warmup)
+        gst = gctx.get_stats()
+        if gst.error_flags or gst.interactions != inter or not torch.equal(gctx._graph_io[2], fixed.acc):
+            raise RuntimeError(f"replay differs from the eager step (flags {gst.error_flags}, "
+                               f"interactions {gst.interactions} vs {inter})")
+        del gctx
+    except (RuntimeError, bh.BHError) as e:
+        step_mode, graph_error, ms_per_step = "eager", str(e), ms_eager
     value = inter / (ms_per_step * 1e-3)
     t_force = stage["force"]
     achieved = FLOPS_PER_INTERACTION * inter / (t_force * 1e-3) / 1e12
@@ -231,6 +249,11 @@ def main():
                    "workload_theta": w.theta, "n_crit": w.n_crit,
                    "theta_mode": "fixed" if calib is None else "fixed, bisected to the target RMS force error"},
         "particles_per_s": n / (ms_per_step * 1e-3),
+        "step": ("one HIP graph replay: tree build, groups, list walk, force sum" if step_mode == "graph"
+                 else f"eager calls (graph replay not used: {graph_error})"),
+        "eager": {"ms_per_step": ms_eager, "interactions_per_s": inter / (ms_eager * 1e-3),
+                  "step": "the same calls issued one by one (the force call waits for the walk to check its "
+                          "list pools)"},
         "interactions_per_step": inter,
         "interactions_per_particle": inter / n,
         "rms_force_error": rms,
