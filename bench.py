@@ -78,6 +78,7 @@ def parse():
     ap.add_argument("--theta-net", default=os.path.join(ROOT, "paper_0909_0541_amd", "theta_net.npz"),
                     help="trained per-group theta network (the learned leg is skipped when missing)")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-particle", action="store_true", help="skip the per-particle walk A/B leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-systems leg")
     ap.add_argument("--copy-check-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the timed steps, "
@@ -161,6 +162,49 @@ def batch_leg(args):
             "step": "one HIP graph replay: build of all 64 trees, groups, list walk, force sum",
             "autotune": [{"n_crit": t.n_crit, "waves_per_cu": t.waves_per_cu, "ms": t.ms_per_step}
                          for t in trials]}
+
+
+def particle_leg(args, ctx, judge, dpos, dmass, w, line):
+    """The paper's own GPU form as an A/B: every particle walks the tree by
+    itself and sums on the way (no groups, no lists); theta bisected to the
+    same RMS error; the step is the tree build plus that walk."""
+    import torch
+
+    from paper_0909_0541_amd import learned
+
+    n = dpos.shape[0]
+
+    def step(th):
+        ctx.build_tree(dpos, dmass)
+        return ctx.compute_forces_particle(w.eps, th)
+
+    def rms_of(th):
+        acc, _ = step(th)
+        return judge.rms(acc)
+
+    theta, r = learned.bisect(rms_of, 0.2, 1.0, args.target_rms)
+    for _ in range(max(args.warmup, 1)):
+        step(theta)
+    torch.cuda.synchronize()
+    ctx.get_stats()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    steps = max(1, min(args.steps, 5))
+    e0.record()
+    for _ in range(steps):
+        step(theta)
+    e1.record()
+    torch.cuda.synchronize()
+    st = ctx.get_stats()
+    if st.error_flags:
+        raise RuntimeError(f"device error flags {st.error_flags}")
+    ms = e0.elapsed_time(e1) / steps
+    return {"theta": theta, "rms_force_error": r, "ms_per_step": ms, "interactions_per_step": st.interactions,
+            "interactions_per_s": st.interactions / (ms * 1e-3), "particles_per_s": n / (ms * 1e-3),
+            "walk_ms": st.t_particle_ms / max(st.n_particle_calls, 1), "max_list": st.max_list,
+            "grouped_speedup": ms / line["ms_per_step"],
+            "interactions_vs_grouped": st.interactions / line["interactions_per_step"],
+            "step": "tree build + per-particle walk and sum (the paper's threaded-tree kernel form)"}
 
 
 def main():
@@ -297,6 +341,8 @@ def main():
             "interactions_per_s": st2.interactions / (ms2 * 1e-3), "particles_per_s": n / (ms2 * 1e-3),
             "interactions_per_step": st2.interactions, "stage_ms": s2,
             "force_kernel_tflops": FLOPS_PER_INTERACTION * st2.interactions / (s2["force"] * 1e-3) / 1e12}
+    if calib is not None and not args.no_particle:
+        line["per_particle"] = particle_leg(args, ctx, judge, dpos, dmass, w, line)
     if not args.no_batch:
         line["batch"] = batch_leg(args)
     if not args.no_cpu_baseline:

@@ -88,6 +88,9 @@ typedef struct {
   int32_t n_segments;      /* last force call: list segments of those groups */
   int32_t n_split_levels;  /* last force call: deepest hand-over level of a split walk (0: none) */
   int32_t n_walk_attempts; /* last force call: walks run (more than 1 when a list pool had to grow) */
+  double t_particle_ms;     /* per-particle walk calls (thread pointers, walk and sum) */
+  int32_t n_particle_calls;
+  int32_t pad;
 } bh_stats;
 
 typedef struct {
@@ -184,6 +187,24 @@ bh_status bh_compute_forces(bh_ctx *ctx, double eps, double theta, const float *
  * particle count, so set bh_options.split_visits explicitly for that). */
 bh_status bh_compute_forces_batch(bh_ctx *ctx, const double *eps_sys, const double *theta_sys,
                                   const float *theta_group, float *acc, float *pot);
+
+/* The paper's own GPU form (Sec. 3.1, Fig. "treegpu"): every particle walks
+ * the tree by itself over a threaded tree ("next" skips a subtree, "more" is
+ * the first child) and sums Eq. (1) on the way, with no shared list.  The
+ * opening test is the group test of bh_compute_forces with one-particle
+ * groups (d = distance from the cell's centre of mass to the particle), so
+ * the terms summed are those of the lists of bh_make_groups(1); the lane's
+ * own particle is skipped.  FP64 test, FP32 terms from the FP64 relative
+ * vector, partial sums folded into FP64.  Needs a tree (not groups).
+ *   eps > 0 (eps^2 a normal FP32 number), theta in [0, 1] (theta = 0: direct
+ *   summation); acc device FP32 [n][3], pot device FP32 [n], input order.
+ * Stats report interactions (list length - 1 per particle), entries and the
+ * longest list as for the group path.  Synchronises once (node count). */
+bh_status bh_compute_forces_particle(bh_ctx *ctx, double eps, double theta, float *acc, float *pot);
+
+/* Same with per-system parameters: eps_sys, theta_sys host FP64 [n_systems]. */
+bh_status bh_compute_forces_particle_batch(bh_ctx *ctx, const double *eps_sys, const double *theta_sys, float *acc,
+                                           float *pot);
 
 /* ---- captured steps (HIP graph) ---------------------------------------- */
 

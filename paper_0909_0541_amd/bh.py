@@ -39,7 +39,8 @@ class _Stats(C.Structure):
                 ("t_walk_ms", C.c_double), ("t_force_ms", C.c_double), ("n_build_calls", C.c_int32),
                 ("n_groups_calls", C.c_int32), ("n_walk_calls", C.c_int32), ("n_force_calls", C.c_int32),
                 ("n_split_groups", C.c_int32), ("n_segments", C.c_int32), ("n_split_levels", C.c_int32),
-                ("n_walk_attempts", C.c_int32)]
+                ("n_walk_attempts", C.c_int32), ("t_particle_ms", C.c_double), ("n_particle_calls", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class _Mlp(C.Structure):
@@ -75,6 +76,8 @@ def load():
         "bh_make_groups": ([vp, i32, C.POINTER(i64)], C.c_int),
         "bh_compute_forces": ([vp, dbl, dbl, vp, vp, vp], C.c_int),
         "bh_compute_forces_batch": ([vp, vp, vp, vp, vp, vp], C.c_int),
+        "bh_compute_forces_particle": ([vp, dbl, dbl, vp, vp], C.c_int),
+        "bh_compute_forces_particle_batch": ([vp, vp, vp, vp, vp], C.c_int),
         "bh_leapfrog": ([vp, i64, vp, vp, vp, C.c_double, C.c_double, i32, C.c_double, i32, vp, vp], C.c_int),
         "bh_get_stats": ([vp, C.POINTER(_Stats)], C.c_int),
         "bh_graph_capture": ([vp, i32, vp, vp, vp, i32, vp, vp, vp, vp, vp], C.c_int),
@@ -141,6 +144,9 @@ class Stats:
     n_segments: int
     n_split_levels: int
     n_walk_attempts: int
+    t_particle_ms: float
+    n_particle_calls: int
+    pad: int
 
 
 class Context:
@@ -255,6 +261,28 @@ class Context:
         self._check(self._L.bh_compute_forces_batch(self._h, e.ctypes.data_as(C.c_void_p),
                                                     t.ctypes.data_as(C.c_void_p), _ptr(theta_group), _ptr(acc),
                                                     _ptr(pot)))
+        return acc, pot
+
+    def compute_forces_particle(self, eps, theta, acc=None, pot=None):
+        """Per-particle walk and sum (no groups, no lists); eps and theta are
+        scalars or one value per system."""
+        import numpy as np
+        n = self.n
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if acc is None:
+            acc = torch.empty((n, 3), dtype=torch.float32, device=dev)
+        if pot is None:
+            pot = torch.empty((n,), dtype=torch.float32, device=dev)
+        _dev(acc, torch.float32, (n, 3), "acc")
+        _dev(pot, torch.float32, (n,), "pot")
+        if np.ndim(eps) == 0 and np.ndim(theta) == 0:
+            self._check(self._L.bh_compute_forces_particle(self._h, float(eps), float(theta), _ptr(acc), _ptr(pot)))
+        else:
+            ns = self.n_systems
+            e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, dtype=np.float64), (ns,)))
+            t = np.ascontiguousarray(np.broadcast_to(np.asarray(theta, dtype=np.float64), (ns,)))
+            self._check(self._L.bh_compute_forces_particle_batch(self._h, e.ctypes.data_as(C.c_void_p),
+                                                                 t.ctypes.data_as(C.c_void_p), _ptr(acc), _ptr(pot)))
         return acc, pot
 
     def graph_capture(self, offsets, pos: torch.Tensor, mass: torch.Tensor, n_crit: int, eps_sys, theta_sys,

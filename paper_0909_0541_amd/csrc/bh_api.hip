@@ -369,7 +369,7 @@ void bh_destroy(bh_ctx *c) {
                     &c->hist, &c->nodes, &c->msum, &c->meta, &c->levels, &c->lcells, &c->gflag, &c->gidx, &c->glen, &c->ginfo, &c->gbox, &c->glist,
                     &c->gmass, &c->bbox_part, &c->sys, &c->par, &c->info, &c->direct_part, &c->energy_part,
                     &c->glists, &c->far_pool, &c->near_pool, &c->far_next, &c->near_next,
-                    &c->items, &c->item_n, &c->item_off, &c->feps, &c->mlp_work, &c->mlp_feat, &c->order_hist, &c->item_order, &c->tasks, &c->ranges, &c->segs,
+                    &c->items, &c->item_n, &c->item_off, &c->feps, &c->mlp_work, &c->mlp_feat, &c->pp_next, &c->order_hist, &c->item_order, &c->tasks, &c->ranges, &c->segs,
                     &c->split_ctr, &c->gsplit, &c->gnseg, &c->gsegfirst, &c->skeys[0], &c->skeys[1], &c->svals[0],
                     &c->svals[1], &c->shist, &c->sscan, &c->srows, &c->spbase, &c->sgroups, &c->psum};
   for (DevBuf *b : bufs) free_buf(*b);
@@ -379,7 +379,7 @@ void bh_destroy(bh_ctx *c) {
   if (c->stage) (void)hipHostFree(c->stage);
   if (c->split_host) (void)hipHostFree(c->split_host);
   if (c->stage_event) (void)hipEventDestroy(c->stage_event);
-  Timer *ts[] = {&c->t_build, &c->t_groups, &c->t_walk, &c->t_force};
+  Timer *ts[] = {&c->t_build, &c->t_groups, &c->t_walk, &c->t_force, &c->t_particle};
   for (Timer *t : ts)
     for (hipEvent_t e : t->ev) (void)hipEventDestroy(e);
   delete c;
@@ -710,6 +710,65 @@ bh_status bh_compute_forces_batch(bh_ctx *c, const double *eps_sys, const double
   return forces_common(c, eps_sys, theta_sys, theta_group, acc, pot);
 }
 
+// The per-particle walk (no groups needed): parameters as for the group path.
+static bh_status particle_common(bh_ctx *c, const double *eps_sys, const double *theta_sys, float *acc,
+                                 float *pot) {
+  if (!c->have_tree) return fail(c, BH_ESTATE, "forces requested before a tree was built");
+  if (c->n > 0 && (!acc || !pot)) return fail(c, BH_EINVAL, "acc and pot must not be NULL");
+  c->par_host.assign((size_t)c->nsys, SysParam{});
+  for (int s = 0; s < c->nsys; ++s) {
+    const double e = eps_sys[s], t = theta_sys[s];
+    if (!(e > 0.0) || !isfinite(e)) return fail(c, BH_EINVAL, "eps must be positive and finite");
+    const float e2 = (float)(e * e);
+    if (!(e2 >= 1.17549435e-38f) || isinf(e2)) return fail(c, BH_EINVAL, "eps^2 must be a normal FP32 number");
+    if (!(t >= 0.0 && t <= 1.0)) return fail(c, BH_EINVAL, "theta must be in [0, 1]");
+    c->par_host[s].eps = e;
+    c->par_host[s].theta = t;
+  }
+  bh_status st = ensure(c, c->par, sizeof(SysParam) * (size_t)c->nsys, "parameters");
+  if (st) return st;
+  st = upload(c, c->par.p, c->par_host.data(), sizeof(SysParam) * (size_t)c->nsys);
+  if (st) return st;
+  st = hip_check(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(DevInfo), hipMemcpyDeviceToHost, c->stream),
+                 "hipMemcpyAsync info");
+  if (st) return st;
+  st = hip_check(c, hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  if (st) return st;
+  const int64_t nslots = (int64_t)c->nsys + c->info_host->n_slots;
+  st = ensure(c, c->pp_next, sizeof(int32_t) * (size_t)std::max<int64_t>(nslots, 1), "thread pointers");
+  if (st) return st;
+  reset_list_counters(P<DevInfo>(c->info), c->stream);
+  st = timer_start(c, c->t_particle);
+  if (st) return st;
+  particle_forces_device(P<NodeRec>(c->nodes), (int)nslots, c->nsys, P<SysInfo>(c->sys), P<SysParam>(c->par),
+                         P<double>(c->spos), P<int32_t>(c->perm), c->n, P<int32_t>(c->pp_next), acc, pot,
+                         P<DevInfo>(c->info), c->stream);
+  st = timer_stop(c, c->t_particle);
+  if (st) return st;
+  st = hip_check(c, hipGetLastError(), "kernel launch (per-particle walk)");
+  if (st) return st;
+  c->have_forces = true;
+  c->last_split_groups = c->last_segments = c->last_depth = 0;
+  c->last_attempts = 1;
+  return BH_OK;
+}
+
+bh_status bh_compute_forces_particle(bh_ctx *c, double eps, double theta, float *acc, float *pot) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (!c->have_tree) return fail(c, BH_ESTATE, "forces requested before a tree was built");
+  std::vector<double> e((size_t)c->nsys, eps), t((size_t)c->nsys, theta);
+  return particle_common(c, e.data(), t.data(), acc, pot);
+}
+
+bh_status bh_compute_forces_particle_batch(bh_ctx *c, const double *eps_sys, const double *theta_sys, float *acc,
+                                           float *pot) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (!eps_sys || !theta_sys) return fail(c, BH_EINVAL, "eps_sys and theta_sys must not be NULL");
+  return particle_common(c, eps_sys, theta_sys, acc, pot);
+}
+
 bh_status bh_graph_capture(bh_ctx *c, int32_t n_systems, const int64_t *offsets, const double *pos,
                            const double *mass, int32_t n_crit, const double *eps_sys, const double *theta_sys,
                            const float *theta_group, float *acc, float *pot) {
@@ -805,6 +864,7 @@ bh_status bh_get_stats(bh_ctx *c, bh_stats *out) {
   out->t_groups_ms = timer_take(c->t_groups, &out->n_groups_calls);
   out->t_walk_ms = timer_take(c->t_walk, &out->n_walk_calls);
   out->t_force_ms = timer_take(c->t_force, &out->n_force_calls);
+  out->t_particle_ms = timer_take(c->t_particle, &out->n_particle_calls);
   return st;
 }
 

@@ -203,6 +203,7 @@ struct bh_ctx {
   bh::DevBuf feps;              // FP64 [nsys] softening of the feature call
   bh::DevBuf mlp_work;          // training batch workspace
   bh::DevBuf mlp_feat;          // FP32 [n][12] features of bh_group_theta
+  bh::DevBuf pp_next;           // int32 per slot: thread pointers of the per-particle walk
   bh::DevBuf order_hist;        // int32 cost bins of the queue orders
   bh::DevBuf item_order;        // int32 queue position -> force item (longest first)
   // split walks: tasks (ping-pong), range pool, segments, counters, per-group
@@ -223,7 +224,7 @@ struct bh_ctx {
   bool stage_event_used = false;
   uint64_t *sorted_keys = nullptr;    // the key buffer holding the sorted keys
 
-  bh::Timer t_build, t_groups, t_walk, t_force;
+  bh::Timer t_build, t_groups, t_walk, t_force, t_particle;
 };
 
 namespace bh {
@@ -330,6 +331,10 @@ struct WalkListArgs {
   int32_t *gsplit;           // per group: 1 when its list is in segments
 };
 void walk_lists_device(const WalkListArgs &a, int grid, hipStream_t s);
+// k_particle.hip: the per-particle walk and sum (no shared lists)
+void particle_forces_device(const NodeRec *nodes, int nslots, int nsys, const SysInfo *sys, const SysParam *par,
+                            const double *spos, const int32_t *perm, int64_t n, int32_t *nxt, float *acc,
+                            float *pot, DevInfo *info, hipStream_t s);
 // k_split.hip: ordering and reduction of split groups
 struct SplitBuffers {
   SplitCounters *ctr;
