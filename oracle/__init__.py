@@ -11,6 +11,8 @@ functions:
   Tree.forces(eps, theta, theta_g=None, groups=None)
                                           -- grouped tree walk + Eq. (1) sums
   Tree.group_list(g, theta)               -- one group's interaction list
+  Tree.second_moments()                   -- per-node second mass moments
+  Tree.forces(..., quadrupole=True)       -- the same sums with quadrupole terms
 """
 from __future__ import annotations
 
@@ -41,6 +43,12 @@ def lib():
         L.oracle_tree_groups.restype = i64
         L.oracle_tree_forces.argtypes = [vp, dbl, dbl, vp, i64, vp, vp, vp, vp, vp, vp, vp]
         L.oracle_tree_forces.restype = C.c_int
+        L.oracle_tree_forces2.argtypes = [vp, dbl, dbl, vp, i64, vp, C.c_int, vp, vp, vp, vp, vp, vp]
+        L.oracle_tree_forces2.restype = C.c_int
+        L.oracle_tree_quadrupoles.argtypes = [vp]
+        L.oracle_tree_quadrupoles.restype = None
+        L.oracle_tree_node_quadrupole.argtypes = [vp, i64, vp]
+        L.oracle_tree_node_quadrupole.restype = None
         L.oracle_tree_group_list.argtypes = [vp, i64, dbl, i64, vp, vp, vp]
         L.oracle_tree_group_list.restype = i64
         L.oracle_tree_info.argtypes = [vp, vp, vp, vp, vp]
@@ -156,11 +164,25 @@ class Tree:
         lib().oracle_tree_group_info(self._h, _p(first), _p(count), _p(lo), _p(hi))
         return first, count, lo, hi
 
-    def forces(self, eps: float, theta: float, theta_g=None, groups=None, lists_only: bool = False):
+    def second_moments(self):
+        """Second mass moments about each node's centre of mass, [nnodes, 6]
+        in the order xx, yy, zz, xy, xz, yz (zero for particles)."""
+        lib().oracle_tree_quadrupoles(self._h)
+        nn = self.info()["nnodes"]
+        out = np.zeros((nn, 6))
+        row = np.zeros(6)
+        for k in range(nn):
+            lib().oracle_tree_node_quadrupole(self._h, k, _p(row))
+            out[k] = row
+        return out
+
+    def forces(self, eps: float, theta: float, theta_g=None, groups=None, lists_only: bool = False,
+               quadrupole: bool = False):
         """Grouped tree forces.  Returns dict with acc [n,3], pot [n] and
         acc_abs [n] (sum of term magnitudes), all in input order with NaN rows
         for particles outside the selected groups, plus list_len, list_mass
-        (per selected group) and interactions.  lists_only skips the sums."""
+        (per selected group) and interactions.  lists_only skips the sums;
+        quadrupole adds the second-order terms of cell entries."""
         if self.ngroups is None:
             raise RuntimeError("call groups(n_crit) first")
         tg = None if theta_g is None else _f64(theta_g)
@@ -176,8 +198,8 @@ class Tree:
         ll = np.zeros(nsel, dtype=np.int64)
         lm = np.zeros(nsel)
         inter = C.c_int64()
-        rc = lib().oracle_tree_forces(self._h, float(eps), float(theta), _p(tg), nsel, _p(gs), _p(acc), _p(pot),
-                                      _p(aab), _p(ll), _p(lm), C.byref(inter))
+        rc = lib().oracle_tree_forces2(self._h, float(eps), float(theta), _p(tg), nsel, _p(gs), int(quadrupole),
+                                       _p(acc), _p(pot), _p(aab), _p(ll), _p(lm), C.byref(inter))
         if rc != 0:
             raise ValueError("oracle_tree_forces failed")
         return {"acc": acc, "pot": pot, "acc_abs": aab, "list_len": ll, "list_mass": lm,

@@ -96,6 +96,7 @@ typedef struct {
   double m, mx[3];      /* total mass and mass-weighted position sums */
   double com[3];        /* centre of mass */
   double l, s;          /* cell side, |geometric centre - centre of mass| */
+  double q[6];          /* second moments about com: xx, yy, zz, xy, xz, yz (oracle_tree_quadrupoles) */
 } orc_node;
 
 typedef struct {
@@ -112,6 +113,7 @@ typedef struct {
   int64_t ngroup, gcap;
   int64_t *gfirst, *gcount;
   double *glo, *ghi;    /* group bounding boxes [G][3] */
+  int have_quad;        /* quadrupoles computed */
 } orc_tree;
 
 /* Bit b of the three cell coordinates, interleaved x, y, z (x most significant). */
@@ -467,6 +469,41 @@ static int walk_rec(const orc_tree *t, int64_t id, const double *glo, const doub
   return 0;
 }
 
+/* Second mass moments of every node about its centre of mass, from the
+ * plain definition over the node's own particles: S_ab = sum m d_a d_b,
+ * d = x - com (the traceless quadrupole is 3 S - tr(S) I).  A particle's are
+ * zero.  The paper keeps only monopoles; the expansion one order further is
+ * an extension of it. */
+void oracle_tree_quadrupoles(void *h) {
+  orc_tree *t = (orc_tree *)h;
+  if (!t || t->have_quad) return;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t id = 0; id < t->nnode; ++id) {
+    orc_node *v = &t->node[id];
+    for (int k = 0; k < 6; ++k) v->q[k] = 0.0;
+    if (v->kind == ORC_PARTICLE) continue;
+    for (int64_t p = v->first; p < v->first + v->count; ++p) {
+      const double m = t->smass[p];
+      const double dx = t->spos[3 * p] - v->com[0], dy = t->spos[3 * p + 1] - v->com[1],
+                   dz = t->spos[3 * p + 2] - v->com[2];
+      v->q[0] += m * dx * dx;
+      v->q[1] += m * dy * dy;
+      v->q[2] += m * dz * dz;
+      v->q[3] += m * dx * dy;
+      v->q[4] += m * dx * dz;
+      v->q[5] += m * dy * dz;
+    }
+  }
+  t->have_quad = 1;
+}
+
+/* Second moments of node id (6 values as above); zeros before they are
+ * computed. */
+void oracle_tree_node_quadrupole(void *h, int64_t id, double *q6) {
+  orc_tree *t = (orc_tree *)h;
+  for (int k = 0; k < 6; ++k) q6[k] = (t && t->have_quad && id >= 0 && id < t->nnode) ? t->node[id].q[k] : 0.0;
+}
+
 /* Interaction list of group g; entries are written as (x, y, z, m) rows, the
  * Morton index of particle entries (-1 for cells) and the source node id.
  * Returns the list length (possibly larger than cap, in which case only cap
@@ -496,11 +533,32 @@ int64_t oracle_tree_group_list(void *h, int64_t g, double theta, int64_t cap, do
  * against which cancellation in acc is measured.  Per selected group k:
  * list_len[k] = list length, list_mass[k] = sum of entry masses (nullable).
  * interactions (nullable) receives sum over members of (list length - 1). */
+int oracle_tree_forces2(void *h, double eps, double theta, const double *theta_g, int64_t nsel,
+                        const int64_t *gsel, int quadrupole, double *acc, double *pot, double *acc_abs,
+                        int64_t *list_len, double *list_mass, int64_t *interactions);
+
 int oracle_tree_forces(void *h, double eps, double theta, const double *theta_g, int64_t nsel,
                        const int64_t *gsel, double *acc, double *pot, double *acc_abs, int64_t *list_len,
                        double *list_mass, int64_t *interactions) {
+  return oracle_tree_forces2(h, eps, theta, theta_g, nsel, gsel, 0, acc, pot, acc_abs, list_len, list_mass,
+                             interactions);
+}
+
+/* As oracle_tree_forces; with quadrupole != 0 a cell entry adds the
+ * second-order term of the Taylor expansion of the softened potential of its
+ * particles about their centre of mass.  With u = com - x_i, R^2 = |u|^2 +
+ * eps^2 and S the cell's second moments, T = tr S:
+ *   pot = -M/R - 3 (u.S.u) / (2 R^5) + T / (2 R^3)
+ * and the acceleration is its gradient in u,
+ *   acc = M u/R^3 - 3 S u/R^5 + (15 (u.S.u) / (2 R^7) - 3 T / (2 R^5)) u.
+ * (For eps = 0 this is the traceless quadrupole form.)  acc_abs still sums
+ * the magnitudes of the monopole parts. */
+int oracle_tree_forces2(void *h, double eps, double theta, const double *theta_g, int64_t nsel,
+                        const int64_t *gsel, int quadrupole, double *acc, double *pot, double *acc_abs,
+                        int64_t *list_len, double *list_mass, int64_t *interactions) {
   orc_tree *t = (orc_tree *)h;
   if (!t) return -1;
+  if (quadrupole) oracle_tree_quadrupoles(t);
   if (gsel == NULL) nsel = t->ngroup;
   double eps2 = eps * eps;
   int64_t total = 0;
@@ -539,6 +597,22 @@ int oracle_tree_forces(void *h, double eps, double theta, const double *theta_g,
           az += mr3 * dz;
           p -= q->m * rinv;
           if (acc_abs) aa += mr3 * sqrt(dx * dx + dy * dy + dz * dz);
+          if (quadrupole && q->particle < 0) {
+            const double *S = t->node[q->node].q;
+            const double sx = S[0] * dx + S[3] * dy + S[4] * dz;
+            const double sy = S[3] * dx + S[1] * dy + S[5] * dz;
+            const double sz = S[4] * dx + S[5] * dy + S[2] * dz;
+            const double usu = dx * sx + dy * sy + dz * sz;
+            const double tr = S[0] + S[1] + S[2];
+            const double r3 = rinv * rinv * rinv;
+            const double r5 = r3 * rinv * rinv;
+            const double r7 = r5 * rinv * rinv;
+            const double c = 7.5 * usu * r7 - 1.5 * tr * r5;
+            ax += -3.0 * sx * r5 + c * dx;
+            ay += -3.0 * sy * r5 + c * dy;
+            az += -3.0 * sz * r5 + c * dz;
+            p += -1.5 * usu * r5 + 0.5 * tr * r3;
+          }
         }
         int64_t o = t->perm[i];
         acc[3 * o] = ax; acc[3 * o + 1] = ay; acc[3 * o + 2] = az;
