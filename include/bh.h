@@ -103,6 +103,15 @@ typedef struct {
                             default, 18 per particle of a walk wave, i.e. 18 n / (CUs x walk
                             waves per CU), at least 12288; -1: never; else >= 64).  Results
                             do not depend on when or where the tasks ran, only on the cap. */
+  int32_t quadrupole;    /* 1: builds also compute every cell's second mass moments S about its
+                            centre of mass (bottom-up, parallel axes, FP64), and bh_compute_forces
+                            and bh_compute_forces_batch add to each cell entry of a list the
+                            second-order term of the softened potential of its particles,
+                            -3 (u.S.u) / (2 R^5) + tr S / (2 R^3) with u = com - x_i,
+                            R^2 = |u|^2 + eps^2, and its gradient, in FP32 (an extension of the
+                            monopole sums of Eq. 1: same lists, same opening test).  Force calls
+                            then need a tree built with the option set (else BH_ESTATE); the
+                            per-particle walk rejects it (BH_EINVAL).  0 (default): monopoles. */
 } bh_options;
 
 /* ---- context ---------------------------------------------------------- */
@@ -343,6 +352,12 @@ bh_status bh_export_sorted(bh_ctx *ctx, uint64_t *keys, int32_t *perm);
  * children; reals device FP64 [slots][6] = mass, centre of mass x, y, z, side
  * l (+inf for buckets), s.  Slot k < n_systems is the root of system k. */
 bh_status bh_export_nodes(bh_ctx *ctx, int32_t *ints, double *reals);
+
+/* Second mass moments of every slot about its centre of mass (tree built
+ * with the quadrupole option, else BH_ESTATE): moments device FP64
+ * [slots][6] = xx, yy, zz, xy, xz, yz, sum m d_a d_b over the node's
+ * particles with d = x - com; zero for particle leaves. */
+bh_status bh_export_moments(bh_ctx *ctx, double *moments);
 
 /* Groups (stats.n_groups): ints device int32 [G][3] = first particle, count,
  * system; box device FP64 [G][6] = lo x, y, z, hi x, y, z.  After a force

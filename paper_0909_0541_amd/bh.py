@@ -51,7 +51,8 @@ MLP_FEATURES, MLP_HIDDEN, MLP_PARAMS = 12, 64, 5057
 
 
 class _Options(C.Structure):
-    _fields_ = [("waves_per_cu", C.c_int32), ("timing", C.c_int32), ("split_visits", C.c_int32)]
+    _fields_ = [("waves_per_cu", C.c_int32), ("timing", C.c_int32), ("split_visits", C.c_int32),
+                ("quadrupole", C.c_int32)]
 
 
 def load():
@@ -93,6 +94,7 @@ def load():
         "bh_energy": ([vp, i64, vp, vp, vp, vp], C.c_int),
         "bh_export_sorted": ([vp, vp, vp], C.c_int),
         "bh_export_nodes": ([vp, vp, vp], C.c_int),
+        "bh_export_moments": ([vp, vp], C.c_int),
         "bh_export_groups": ([vp, vp, vp, vp, vp], C.c_int),
     }
     for name, (args, res) in sigs.items():
@@ -153,7 +155,7 @@ class Context:
     """A bh_ctx bound to a torch stream (the current stream by default)."""
 
     def __init__(self, stream: torch.cuda.Stream | None = None, waves_per_cu: int | None = None,
-                 timing: bool = False, split_visits: int | None = None):
+                 timing: bool = False, split_visits: int | None = None, quadrupole: bool = False):
         self._L = load()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: libbh runs only on the device")
@@ -170,6 +172,7 @@ class Context:
         opt.timing = 1 if timing else 0
         if split_visits is not None:
             opt.split_visits = int(split_visits)
+        opt.quadrupole = 1 if quadrupole else 0
         self._check(self._L.bh_set_options(self._h, C.byref(opt)))
 
     def _check(self, st, h=0):
@@ -191,7 +194,7 @@ class Context:
             pass
 
     def set_options(self, waves_per_cu: int | None = None, timing: bool | None = None,
-                    split_visits: int | None = None):
+                    split_visits: int | None = None, quadrupole: bool | None = None):
         opt = _Options()
         self._check(self._L.bh_get_options(self._h, C.byref(opt)))
         if waves_per_cu is not None:
@@ -200,6 +203,8 @@ class Context:
             opt.timing = 1 if timing else 0
         if split_visits is not None:
             opt.split_visits = int(split_visits)
+        if quadrupole is not None:
+            opt.quadrupole = 1 if quadrupole else 0
         self._check(self._L.bh_set_options(self._h, C.byref(opt)))
 
     def sync(self):
@@ -451,6 +456,16 @@ class Context:
         reals = torch.empty((st.n_slots, 6), dtype=torch.float64, device=dev)
         self._check(self._L.bh_export_nodes(self._h, _ptr(ints), _ptr(reals)))
         return ints, reals
+
+    def export_moments(self):
+        """Second mass moments about each node's centre of mass, FP64
+        [n_slots, 6] (xx, yy, zz, xy, xz, yz; zero for particle leaves).
+        Needs a tree built with the quadrupole option."""
+        st = self.get_stats()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        out = torch.empty((st.n_slots, 6), dtype=torch.float64, device=dev)
+        self._check(self._L.bh_export_moments(self._h, _ptr(out)))
+        return out
 
     def export_groups(self, lists: bool = False):
         st = self.get_stats()

@@ -49,6 +49,17 @@ __global__ void k_export_nodes(const NodeRec *__restrict__ nodes, const int8_t *
   }
 }
 
+// Second moments per slot; zero for particle leaves and empty roots (their
+// rows of qmom are never written).
+__global__ void k_export_moments(const NodeRec *__restrict__ nodes, const double *__restrict__ qmom,
+                                 const DevInfo *__restrict__ info, int nsys, double *__restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t slots = (int64_t)nsys + info->n_slots;
+  if (k >= slots) return;
+  const bool leaf = nodes[k].child < 0;
+  for (int j = 0; j < 6; ++j) out[6 * k + j] = leaf ? 0.0 : qmom[6 * k + j];
+}
+
 __global__ void k_copy_keys(const uint64_t *__restrict__ src, uint64_t *__restrict__ dst, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[i];
@@ -312,6 +323,16 @@ static bh_status build_common(bh_ctx *c, int32_t nsys, const int64_t *offsets, c
   B.lcursor = B.lcount + 48;
   B.lcells = P<int32_t>(c->lcells);
   B.slot_cap = (int64_t)std::min({c->nodes.bytes / sizeof(NodeRec), c->msum.bytes / 32, c->meta.bytes});
+  const bool quad = c->opt.quadrupole != 0;
+  if (quad) {
+    const size_t slots = (size_t)B.slot_cap;
+    st = ensure(c, c->qmom, 48 * slots, "second moments");
+    if (st) return st;
+    st = ensure(c, c->qpack, 32 * slots, "packed second moments");
+    if (st) return st;
+    B.qmom = P<double>(c->qmom);
+    B.qpack = P<float4>(c->qpack);
+  }
   build_tree_device(B, c->stream);
   c->sorted_keys = B.sorted_keys;
   st = timer_stop(c, c->t_build);
@@ -319,6 +340,7 @@ static bh_status build_common(bh_ctx *c, int32_t nsys, const int64_t *offsets, c
   st = hip_check(c, hipGetLastError(), "kernel launch (build)");
   if (st) return st;
   c->have_tree = true;
+  c->have_quad = quad;
   return BH_OK;
 }
 
@@ -404,6 +426,7 @@ bh_status bh_set_options(bh_ctx *c, const bh_options *opt) {
   if (opt->waves_per_cu < 0 || opt->waves_per_cu > 32) return fail(c, BH_EINVAL, "waves_per_cu must be in [0, 32]");
   if (opt->split_visits < -1 || (opt->split_visits > 0 && opt->split_visits < 64))
     return fail(c, BH_EINVAL, "split_visits must be -1, 0 or >= 64");
+  if (opt->quadrupole != 0 && opt->quadrupole != 1) return fail(c, BH_EINVAL, "quadrupole must be 0 or 1");
   c->opt = *opt;
   return BH_OK;
 }
@@ -479,6 +502,9 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
                                float *acc, float *pot) {
   if (!c->have_groups) return fail(c, BH_ESTATE, "forces requested before bh_make_groups");
   if (c->n > 0 && (!acc || !pot)) return fail(c, BH_EINVAL, "acc and pot must not be NULL");
+  const bool quad = c->opt.quadrupole != 0;
+  if (quad && !c->have_quad)
+    return fail(c, BH_ESTATE, "quadrupole sums need a tree built with the quadrupole option set");
   c->par_host.assign((size_t)c->nsys, SysParam{});
   for (int s = 0; s < c->nsys; ++s) {
     const double e = eps_sys[s], t = theta_sys[s];
@@ -515,12 +541,13 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
   W.gmass = P<double>(c->gmass);
   if (!c->walk_bpc) {
     c->walk_bpc = walk_lists_blocks_per_cu();
-    c->force_bpc = force_lists_blocks_per_cu();
+    c->force_bpc = force_lists_blocks_per_cu(false);
+    c->force_bpc_q = force_lists_blocks_per_cu(true);
   }
   const size_t gcap = (size_t)std::max<int64_t>(c->n, 1);
   // split walks (long lists walked and summed by several waves)
   const int grid = c->num_cu * (c->opt.waves_per_cu > 0 ? c->opt.waves_per_cu : c->walk_bpc);
-  const int fgrid = c->num_cu * (c->opt.waves_per_cu > 0 ? c->opt.waves_per_cu : c->force_bpc);
+  const int fgrid = c->num_cu * (c->opt.waves_per_cu > 0 ? c->opt.waves_per_cu : (quad ? c->force_bpc_q : c->force_bpc));
   // The default visit cap scales with the particles per walk wave (a walk
   // that outlasts the average wave's share of the walk is the one to split;
   // that share grows with the particles per wave), never below kSplitVisits.
@@ -543,6 +570,10 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
     if (st) return st;
     st = ensure(c, c->far_next, (size_t)c->far_cap * sizeof(int32_t), "far list links");
     if (st) return st;
+    if (quad) {
+      st = ensure(c, c->far_slot, (size_t)c->far_cap * kFarChunk * sizeof(int32_t), "far list node slots");
+      if (st) return st;
+    }
     st = ensure(c, c->near_pool, (size_t)c->near_cap * 2 * kNearChunk * sizeof(float4), "near list pool");
     if (st) return st;
     st = ensure(c, c->near_next, (size_t)c->near_cap * sizeof(int32_t), "near list links");
@@ -566,6 +597,7 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
     W.near_pool = P<float4>(c->near_pool);
     W.far_next = P<int32_t>(c->far_next);
     W.near_next = P<int32_t>(c->near_next);
+    W.far_slot = quad ? P<int32_t>(c->far_slot) : nullptr;
     W.far_cap = c->far_cap;
     W.near_cap = c->near_cap;
     W.glists = P<int32_t>(c->glists);
@@ -665,6 +697,8 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
   F.near_pool = P<float4>(c->near_pool);
   F.far_next = P<int32_t>(c->far_next);
   F.near_next = P<int32_t>(c->near_next);
+  F.far_slot = quad ? P<int32_t>(c->far_slot) : nullptr;
+  F.qpack = quad ? P<float4>(c->qpack) : nullptr;
   F.spos = P<double>(c->spos);
   F.smass = P<double>(c->smass);
   F.perm = P<int32_t>(c->perm);
@@ -715,6 +749,7 @@ static bh_status particle_common(bh_ctx *c, const double *eps_sys, const double 
                                  float *pot) {
   if (!c->have_tree) return fail(c, BH_ESTATE, "forces requested before a tree was built");
   if (c->n > 0 && (!acc || !pot)) return fail(c, BH_EINVAL, "acc and pot must not be NULL");
+  if (c->opt.quadrupole) return fail(c, BH_EINVAL, "the per-particle walk sums monopoles only (quadrupole option set)");
   c->par_host.assign((size_t)c->nsys, SysParam{});
   for (int s = 0; s < c->nsys; ++s) {
     const double e = eps_sys[s], t = theta_sys[s];
@@ -1072,6 +1107,18 @@ bh_status bh_export_nodes(bh_ctx *c, int32_t *ints, double *reals) {
   k_export_nodes<<<blocks_for(cap), 256, 0, c->stream>>>(P<NodeRec>(c->nodes), P<int8_t>(c->meta),
                                                           P<DevInfo>(c->info), c->nsys, ints, reals);
   return hip_check(c, hipGetLastError(), "kernel launch (export nodes)");
+}
+
+bh_status bh_export_moments(bh_ctx *c, double *moments) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (!c->have_tree) return fail(c, BH_ESTATE, "no tree");
+  if (!c->have_quad) return fail(c, BH_ESTATE, "the tree was built without the quadrupole option");
+  if (!moments) return fail(c, BH_EINVAL, "moments must not be NULL");
+  const int64_t cap = 2 * std::max<int64_t>(c->n, 1) + c->nsys + 1;
+  k_export_moments<<<blocks_for(cap), 256, 0, c->stream>>>(P<NodeRec>(c->nodes), P<double>(c->qmom),
+                                                            P<DevInfo>(c->info), c->nsys, moments);
+  return hip_check(c, hipGetLastError(), "kernel launch (export moments)");
 }
 
 bh_status bh_export_groups(bh_ctx *c, int32_t *ints, double *box, int32_t *list_len, double *list_mass) {

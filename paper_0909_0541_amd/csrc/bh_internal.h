@@ -143,8 +143,8 @@ struct bh_ctx {
   int device = 0;
   int num_cu = 0;
   std::string err;
-  bh_options opt{0, 0, 0};
-  int walk_bpc = 0, force_bpc = 0, probe_bpc = 0;  // resident blocks per CU of the persistent kernels
+  bh_options opt{0, 0, 0, 0};
+  int walk_bpc = 0, force_bpc = 0, force_bpc_q = 0, probe_bpc = 0;  // resident blocks per CU of the persistent kernels
 
   // current tree
   int64_t n = 0;
@@ -152,6 +152,7 @@ struct bh_ctx {
   bool have_tree = false;
   bool have_groups = false;
   bool have_forces = false;
+  bool have_quad = false;  // the current tree carries second moments
   bool capturing = false;         // recording a step into a HIP graph: no uploads, syncs or timers
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t graph = nullptr; // the captured step
@@ -179,6 +180,9 @@ struct bh_ctx {
   bh::DevBuf hist;              // radix histograms
   bh::DevBuf nodes;             // NodeRec [slots]
   bh::DevBuf msum;              // FP64 [slots][4] raw sums m, m x, m y, m z
+  bh::DevBuf qmom;              // FP64 [slots][6] second moments about the centre of mass (quadrupole option)
+  bh::DevBuf qpack;             // FP32 [slots][8] the same and their trace, as read by the force sum
+  bh::DevBuf far_slot;          // int32 per far-pool entry: node slot of a cell entry, -1 a particle
   bh::DevBuf meta;              // int8 [slots] 32 * kind + level (inspection only)
   bh::DevBuf levels;            // int32 level counts, offsets and cursors (3 x 24)
   bh::DevBuf lcells;            // int32 cells grouped by level
@@ -272,6 +276,8 @@ struct TreeBuffers {
   int32_t *owner, *cfirst, *ccount, *cparent, *pparent, *mask, *nchild, *cfc, *cslot;
   NodeRec *nodes;
   double *msum;
+  double *qmom;           // nullable: FP64 [slots][6] second moments (xx, yy, zz, xy, xz, yz)
+  float4 *qpack;          // with qmom: FP32 [slots][2] (xx, yy, zz, xy), (xz, yz, trace, 0)
   int8_t *meta;           // per slot: 32 * kind + level (export only)
   int32_t *lcount, *loff, *lcursor;  // cells per level: counts, offsets [23], scatter cursors
   int32_t *lcells;                   // cell owner positions grouped by level
@@ -318,6 +324,7 @@ struct WalkListArgs {
   int32_t *glists;
   int32_t *glist;
   double *gmass;
+  int32_t *far_slot;         // nullable: node slot of each far entry (-1 a particle), for quadrupoles
   // split walks
   int visit_cap;             // node tests before a walk hands over its stack (0: never)
   SplitCounters *ctr;
@@ -398,13 +405,15 @@ struct ForceArgs {
   const int32_t *gsegfirst;   // group -> first sorted position
   const int32_t *pbase;       // sorted position -> first partial-sum row
   double *psum;               // [rows][4] ax, ay, az, pot
+  const int32_t *far_slot;    // quadrupole sums: node slot of each far entry (near entries: residue .w)
+  const float4 *qpack;        // quadrupole sums: [slots][2] second moments
 };
 void force_items_device(const int32_t *ginfo, const int32_t *gsplit, const int32_t *gnseg, const int32_t *glist,
                         DevInfo *info, int64_t cap, int32_t *nblk, int32_t *off, int32_t *items, void *scan_tmp,
                         hipStream_t s);
 void force_lists_device(const ForceArgs &a, int grid, hipStream_t s);
 void item_order_device(const ForceArgs &f, int64_t cap, int32_t *hist, int32_t *order, hipStream_t s);
-int force_lists_blocks_per_cu();
+int force_lists_blocks_per_cu(bool quad);
 void reset_list_counters(DevInfo *info, hipStream_t s);
 
 // k_misc.hip

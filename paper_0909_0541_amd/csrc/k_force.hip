@@ -14,6 +14,14 @@
 // apart.  After each list chunk the FP32 partial sums are folded into FP64.  A
 // member's own entry is in the near list with dx = 0 exactly: it adds 0 force
 // and m_i/eps potential, removed at the end.
+//
+// Quadrupole sums (a template variant): a cell entry also adds the
+// second-order term of the softened potential of its particles about their
+// centre of mass, from the cell's second moments S (FP32, read by node slot:
+// far entries carry the slot in a parallel array, near entries in the .w of
+// their residue).  With u = dx, R^-1 as above and T = tr S:
+//   potential  -3 (u.S.u) / (2 R^5) + T / (2 R^3)
+//   force      -3 S u / R^5 + (15 (u.S.u) / (2 R^7) - 3 T / (2 R^5)) u.
 #include "bh_device.h"
 
 namespace bh {
@@ -27,11 +35,37 @@ struct Member {
   double dx, dy, dz, dp;
 };
 
+// The quadrupole term of one cell entry (S, T from qpack) at relative
+// position (dx, dy, dz) with ri = 1/R.
+__device__ __forceinline__ void quad_term(Member &M, const float4 *__restrict__ qpack, int slot, float dx, float dy,
+                                          float dz, float ri) {
+  const float4 a = qpack[2 * (int64_t)slot], b = qpack[2 * (int64_t)slot + 1];
+  // a = (xx, yy, zz, xy), b = (xz, yz, trace, 0)
+  const float sx = __builtin_fmaf(a.x, dx, __builtin_fmaf(a.w, dy, b.x * dz));
+  const float sy = __builtin_fmaf(a.w, dx, __builtin_fmaf(a.y, dy, b.y * dz));
+  const float sz = __builtin_fmaf(b.x, dx, __builtin_fmaf(b.y, dy, a.z * dz));
+  const float usu = __builtin_fmaf(dx, sx, __builtin_fmaf(dy, sy, dz * sz));
+  const float r2 = ri * ri;
+  const float r3 = ri * r2;
+  const float r5 = r3 * r2;
+  const float r7 = r5 * r2;
+  const float c = __builtin_fmaf(7.5f * usu, r7, -1.5f * b.z * r5);
+  const float k = -3.0f * r5;
+  M.ax = __builtin_fmaf(k, sx, __builtin_fmaf(c, dx, M.ax));
+  M.ay = __builtin_fmaf(k, sy, __builtin_fmaf(c, dy, M.ay));
+  M.az = __builtin_fmaf(k, sz, __builtin_fmaf(c, dz, M.az));
+  // pt accumulates -potential
+  M.pt = __builtin_fmaf(1.5f * usu, r5, __builtin_fmaf(-0.5f * b.z, r3, M.pt));
+}
+
 // U entries (value e, rounding residue l when NEAR) against this lane's
-// member, written stage by stage across the U independent terms.
-template <int U, bool NEAR>
-__device__ __forceinline__ void terms(Member &M, const float4 (&e)[U], const float4 (&l)[U], float eps2) {
-  float dx[U], dy[U], dz[U], q[U], mr[U];
+// member, written stage by stage across the U independent terms.  With QUAD,
+// sl[u] is the node slot of a far entry (near entries: l[u].w), -1 for a
+// particle.
+template <int U, bool NEAR, bool QUAD = false>
+__device__ __forceinline__ void terms(Member &M, const float4 (&e)[U], const float4 (&l)[U], float eps2,
+                                      const int (&sl)[U], const float4 *__restrict__ qpack) {
+  float dx[U], dy[U], dz[U], q[U], mr[U], ri[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     dx[u] = e[u].x - M.x;
@@ -54,6 +88,10 @@ __device__ __forceinline__ void terms(Member &M, const float4 (&e)[U], const flo
   for (int u = 0; u < U; ++u) q[u] = __builtin_fmaf(dz[u], dz[u], q[u]);
 #pragma unroll
   for (int u = 0; u < U; ++u) q[u] = __builtin_amdgcn_rsqf(q[u]);  // 1/r
+  if (QUAD) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) ri[u] = q[u];
+  }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     mr[u] = e[u].w * q[u];
@@ -67,6 +105,13 @@ __device__ __forceinline__ void terms(Member &M, const float4 (&e)[U], const flo
     M.ay = __builtin_fmaf(q[u], dy[u], M.ay);
     M.az = __builtin_fmaf(q[u], dz[u], M.az);
     M.pt += mr[u];
+  }
+  if (QUAD) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int slot = NEAR ? __float_as_int(l[u].w) : sl[u];
+      if (slot >= 0) quad_term(M, qpack, slot, dx[u], dy[u], dz[u], ri[u]);
+    }
   }
 }
 
@@ -82,34 +127,51 @@ constexpr int kU = 8;  // entries per block of terms
 
 // One chunk with R lane partitions: partition `part` takes entries part,
 // part + R, ...; R is a compile-time constant so that the four entries of a
-// block are loaded at constant offsets from one running pointer.
-template <bool NEAR, int R>
+// block are loaded at constant offsets from one running pointer.  hs: the
+// node slots of far entries (QUAD only).
+template <bool NEAR, int R, bool QUAD>
 __device__ __forceinline__ void chunk_part(Member &M, const float4 *__restrict__ h, const float4 *__restrict__ l,
-                                           int n, int part, float eps2) {
+                                           const int *__restrict__ hs, const float4 *__restrict__ qpack, int n,
+                                           int part, float eps2) {
   const int mine = (n - part + R - 1) / R;
   const float4 *ph = h + part;
   const float4 *pl = l + part;
+  const int *ps = QUAD && !NEAR ? hs + part : nullptr;
   int t = 0;
   for (; t + 4 <= mine; t += 4, ph += 4 * R, pl += 4 * R) {
     float4 e4[4], r4[4];
+    int s4[4] = {-1, -1, -1, -1};
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       e4[u] = ph[u * R];
       r4[u] = NEAR ? pl[u * R] : e4[u];
+      if (QUAD && !NEAR) s4[u] = ps[u * R];
     }
-    terms<4, NEAR>(M, e4, r4, eps2);
+    if (QUAD && !NEAR) ps += 4 * R;
+    terms<4, NEAR, QUAD>(M, e4, r4, eps2, s4, qpack);
   }
   for (; t < mine; ++t, ph += R, pl += R) {
     const float4 e1[1] = {ph[0]}, r1[1] = {NEAR ? pl[0] : ph[0]};
-    terms<1, NEAR>(M, e1, r1, eps2);
+    int s1[1] = {-1};
+    if (QUAD && !NEAR) {
+      s1[0] = ps[0];
+      ps += R;
+    }
+    terms<1, NEAR, QUAD>(M, e1, r1, eps2, s1, qpack);
   }
 }
 
-// n entries of one chunk: values at h[0..n), residues at l[0..n) when NEAR.
-template <bool NEAR>
+// n entries of one chunk: values at h[0..n), residues at l[0..n) when NEAR,
+// node slots at hs[0..n) for far entries with QUAD.
+template <bool NEAR, bool QUAD = false>
 __device__ __forceinline__ void chunk_sum(Member &M, const float4 *__restrict__ h, const float4 *__restrict__ l,
-                                          int n, int R, int part, float eps2) {
+                                          int n, int R, int part, float eps2, const int *__restrict__ hs = nullptr,
+                                          const float4 *__restrict__ qpack = nullptr) {
+  constexpr bool FS = QUAD && !NEAR;  // far slots to load
   float4 e[kU], r[kU];
+  int sl[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) sl[u] = -1;
   if (R == 1) {
     // every lane takes the same entries: scalar loads, scalar operands; the
     // next block is fetched while the current one is summed
@@ -119,48 +181,57 @@ __device__ __forceinline__ void chunk_sum(Member &M, const float4 *__restrict__ 
       for (int u = 0; u < kU; ++u) {
         e[u] = h[u];
         r[u] = NEAR ? l[u] : e[u];
+        if (FS) sl[u] = hs[u];
       }
       for (t = kU; t + kU <= n; t += kU) {
         float4 ne[kU], nr[kU];
+        int ns[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
           ne[u] = h[t + u];
           nr[u] = NEAR ? l[t + u] : ne[u];
+          ns[u] = FS ? hs[t + u] : -1;
         }
-        terms<kU, NEAR>(M, e, r, eps2);
+        terms<kU, NEAR, QUAD>(M, e, r, eps2, sl, qpack);
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
           e[u] = ne[u];
           r[u] = nr[u];
+          sl[u] = ns[u];
         }
       }
-      terms<kU, NEAR>(M, e, r, eps2);
+      terms<kU, NEAR, QUAD>(M, e, r, eps2, sl, qpack);
     }
     for (; t < n; ++t) {
       const float4 e1[1] = {h[t]}, r1[1] = {NEAR ? l[t] : h[t]};
-      terms<1, NEAR>(M, e1, r1, eps2);
+      const int s1[1] = {FS ? hs[t] : -1};
+      terms<1, NEAR, QUAD>(M, e1, r1, eps2, s1, qpack);
     }
   } else {
     switch (R) {
-      case 2: chunk_part<NEAR, 2>(M, h, l, n, part, eps2); break;
-      case 4: chunk_part<NEAR, 4>(M, h, l, n, part, eps2); break;
-      case 8: chunk_part<NEAR, 8>(M, h, l, n, part, eps2); break;
-      case 16: chunk_part<NEAR, 16>(M, h, l, n, part, eps2); break;
-      case 32: chunk_part<NEAR, 32>(M, h, l, n, part, eps2); break;
-      default: chunk_part<NEAR, 64>(M, h, l, n, part, eps2); break;
+      case 2: chunk_part<NEAR, 2, QUAD>(M, h, l, hs, qpack, n, part, eps2); break;
+      case 4: chunk_part<NEAR, 4, QUAD>(M, h, l, hs, qpack, n, part, eps2); break;
+      case 8: chunk_part<NEAR, 8, QUAD>(M, h, l, hs, qpack, n, part, eps2); break;
+      case 16: chunk_part<NEAR, 16, QUAD>(M, h, l, hs, qpack, n, part, eps2); break;
+      case 32: chunk_part<NEAR, 32, QUAD>(M, h, l, hs, qpack, n, part, eps2); break;
+      default: chunk_part<NEAR, 64, QUAD>(M, h, l, hs, qpack, n, part, eps2); break;
     }
   }
   fold(M);
 }
 
 // The list data is read-only here; as separate restrict arguments the
-// compiler can fetch wave-uniform entries with scalar loads.
+// compiler can fetch wave-uniform entries with scalar loads.  QUAD: the
+// quadrupole variant (far_slot and qpack set).
+template <bool QUAD>
 __global__ __launch_bounds__(kWave) void k_force_lists(ForceArgs a, const float4 *__restrict__ far_pool,
                                                        const int32_t *__restrict__ far_next,
                                                        const float4 *__restrict__ near_pool,
                                                        const int32_t *__restrict__ near_next,
                                                        const int32_t *__restrict__ glists,
-                                                       const int32_t *__restrict__ items) {
+                                                       const int32_t *__restrict__ items,
+                                                       const int32_t *__restrict__ far_slot,
+                                                       const float4 *__restrict__ qpack) {
   const int lane = lane_id();
   const int T = a.info->n_items;
   for (;;) {
@@ -226,7 +297,8 @@ __global__ __launch_bounds__(kWave) void k_force_lists(ForceArgs a, const float4
     for (int left = fn; left > 0;) {
       const int n = min(left, kFarChunk);
       const float4 *base = far_pool + (int64_t)ch * kFarChunk;
-      chunk_sum<false>(M, base, base, n, R, part, eps2);
+      chunk_sum<false, QUAD>(M, base, base, n, R, part, eps2, QUAD ? far_slot + (int64_t)ch * kFarChunk : nullptr,
+                             qpack);
       left -= n;
       if (left > 0) ch = far_next[ch];
     }
@@ -234,7 +306,7 @@ __global__ __launch_bounds__(kWave) void k_force_lists(ForceArgs a, const float4
     for (int left = nn; left > 0;) {
       const int n = min(left, kNearChunk);
       const float4 *base = near_pool + (int64_t)ch * (2 * kNearChunk);
-      chunk_sum<true>(M, base, base + kNearChunk, n, R, part, eps2);
+      chunk_sum<true, QUAD>(M, base, base + kNearChunk, n, R, part, eps2, nullptr, qpack);
       left -= n;
       if (left > 0) ch = near_next[ch];
     }
@@ -333,15 +405,21 @@ void force_items_device(const int32_t *ginfo, const int32_t *gsplit, const int32
   k_item_fill<<<blocks, 256, 0, s>>>(ginfo, gsplit, gnseg, off, info, items);
 }
 
-int force_lists_blocks_per_cu() {
+int force_lists_blocks_per_cu(bool quad) {
   int b = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_force_lists, kWave, 0) != hipSuccess || b < 1) b = 8;
+  const hipError_t e = quad ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_force_lists<true>, kWave, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_force_lists<false>, kWave, 0);
+  if (e != hipSuccess || b < 1) b = 8;
   return b;
 }
 
 void force_lists_device(const ForceArgs &a, int grid, hipStream_t s) {
-  k_force_lists<<<(unsigned)grid, kWave, 0, s>>>(a, a.far_pool, a.far_next, a.near_pool, a.near_next, a.glists,
-                                                 a.items);
+  if (a.far_slot && a.qpack)
+    k_force_lists<true><<<(unsigned)grid, kWave, 0, s>>>(a, a.far_pool, a.far_next, a.near_pool, a.near_next,
+                                                         a.glists, a.items, a.far_slot, a.qpack);
+  else
+    k_force_lists<false><<<(unsigned)grid, kWave, 0, s>>>(a, a.far_pool, a.far_next, a.near_pool, a.near_next,
+                                                          a.glists, a.items, nullptr, nullptr);
 }
 
 }  // namespace bh

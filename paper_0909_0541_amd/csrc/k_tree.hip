@@ -448,6 +448,7 @@ __global__ void k_moments(int lev, const int32_t *__restrict__ lcells, const int
                           const int32_t *__restrict__ cfirst, const int32_t *__restrict__ ccount,
                           const uint64_t *__restrict__ keys, const SysInfo *__restrict__ sys, int nsys, int64_t n,
                           int64_t cap, NodeRec *__restrict__ nodes, double *__restrict__ msum,
+                          double *__restrict__ qmom, float4 *__restrict__ qpack,
                           int8_t *__restrict__ meta, DevInfo *info) {
   const int64_t end = loff[lev + 1];
   for (int64_t k = (int64_t)loff[lev] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < end;
@@ -509,6 +510,26 @@ __global__ void k_moments(int lev, const int32_t *__restrict__ lcells, const int
   r.first = cfirst[j];
   r.count = ccount[j];
   nodes[slot] = r;
+  if (qmom) {
+    // second moments about the centre of mass from the children's own, each
+    // shifted to this centre (parallel axes); a particle's own are zero
+    double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int ci = 0; ci < nc; ++ci) {
+      const int cs = c0 + ci;
+      const NodeRec &q = nodes[cs];
+      const double mc = q.m;
+      const double ex = __dsub_rn(q.com[0], com[0]), ey = __dsub_rn(q.com[1], com[1]),
+                   ez = __dsub_rn(q.com[2], com[2]);
+      const double sh[6] = {mc * ex * ex, mc * ey * ey, mc * ez * ez, mc * ex * ey, mc * ex * ez, mc * ey * ez};
+      const bool leaf = q.child < 0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) S[k] = __dadd_rn(S[k], leaf ? sh[k] : __dadd_rn(qmom[6 * (int64_t)cs + k], sh[k]));
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) qmom[6 * (int64_t)slot + k] = S[k];
+    qpack[2 * (int64_t)slot] = make_float4((float)S[0], (float)S[1], (float)S[2], (float)S[3]);
+    qpack[2 * (int64_t)slot + 1] = make_float4((float)S[4], (float)S[5], (float)(S[0] + S[1] + S[2]), 0.0f);
+  }
   meta[slot] = (int8_t)(lev == kKeyLevels ? 32 * kBucket + lev : lev);
   }
 }
@@ -572,7 +593,7 @@ void build_tree_device(TreeBuffers &B, hipStream_t s) {
     k_moments<<<mgrid, 256, 0, s>>>(lev, B.lcells, B.loff, B.level, B.cparent,
                                                                         B.cslot, B.cfc, B.nchild, B.cfirst, B.ccount,
                                                                         keys, B.sys, nsys, n, B.slot_cap, B.nodes,
-                                                                        B.msum, B.meta, B.info);
+                                                                        B.msum, B.qmom, B.qpack, B.meta, B.info);
 }
 
 }  // namespace bh

@@ -385,9 +385,11 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
                          rz = __dsub_rn(r.com[2], cen[2]);
             hi4 = make_float4((float)rx, (float)ry, (float)rz, (float)r.m);
             near = d2 <= near2;
+            // (a near entry's residue carries in .w the node slot of a cell, -1
+            // for a particle, for the quadrupole sums)
             if (near)
               lo4 = make_float4((float)__dsub_rn(rx, (double)hi4.x), (float)__dsub_rn(ry, (double)hi4.y),
-                                (float)__dsub_rn(rz, (double)hi4.z), 0.0f);
+                                (float)__dsub_rn(rz, (double)hi4.z), __int_as_float(r.child < 0 ? -1 : ncur));
             lmass += r.m;
           }
           if (push) rng = make_int2(r.child, r.nchild);
@@ -405,7 +407,9 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
           fok = reserve(F, nf, kFarChunk, fsrc, &a.info->far_chunks, a.far_cap, a.far_next, lane, fok);
           if (fok && emit && !near) {
             const int pos = F.count + rank_below(fm);
-            a.far_pool[(int64_t)chunk_of(F, pos, kFarChunk) * kFarChunk + pos % kFarChunk] = hi4;
+            const int64_t at = (int64_t)chunk_of(F, pos, kFarChunk) * kFarChunk + pos % kFarChunk;
+            a.far_pool[at] = hi4;
+            if (a.far_slot) a.far_slot[at] = rcur.child < 0 ? -1 : ncur;
           }
           F.count += nf;
         }
