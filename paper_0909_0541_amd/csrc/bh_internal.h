@@ -181,7 +181,7 @@ struct bh_ctx {
   bh::DevBuf nodes;             // NodeRec [slots]
   bh::DevBuf msum;              // FP64 [slots][4] raw sums m, m x, m y, m z
   bh::DevBuf qmom;              // FP64 [slots][6] second moments about the centre of mass (quadrupole option)
-  bh::DevBuf qpack;             // FP32 [slots][8] the same and their trace, as read by the force sum
+  bh::DevBuf qpack;             // FP32 [slots][8] 3 x the same, the trace T and 1.5 T, as read by the force sum
   bh::DevBuf far_slot;          // int32 per far-pool entry: node slot of a cell entry, -1 a particle
   bh::DevBuf meta;              // int8 [slots] 32 * kind + level (inspection only)
   bh::DevBuf levels;            // int32 level counts, offsets and cursors (3 x 24)
@@ -277,7 +277,7 @@ struct TreeBuffers {
   NodeRec *nodes;
   double *msum;
   double *qmom;           // nullable: FP64 [slots][6] second moments (xx, yy, zz, xy, xz, yz)
-  float4 *qpack;          // with qmom: FP32 [slots][2] (xx, yy, zz, xy), (xz, yz, trace, 0)
+  float4 *qpack;          // with qmom: FP32 [slots][2] 3 (xx, yy, zz, xy), (3 xz, 3 yz, T, 1.5 T), T the trace
   int8_t *meta;           // per slot: 32 * kind + level (export only)
   int32_t *lcount, *loff, *lcursor;  // cells per level: counts, offsets [23], scatter cursors
   int32_t *lcells;                   // cell owner positions grouped by level

@@ -17,9 +17,9 @@
 //
 // Quadrupole sums (a template variant): a cell entry also adds the
 // second-order term of the softened potential of its particles about their
-// centre of mass, from the cell's second moments S (FP32, read by node slot:
-// far entries carry the slot in a parallel array, near entries in the .w of
-// their residue).  With u = dx, R^-1 as above and T = tr S:
+// centre of mass, from the cell's second moments S (FP32, packed as 3 S and
+// the trace, read by node slot: far entries carry the slot in a parallel
+// array, near entries in the .w of their residue).  With u = dx, R^-1 as above and T = tr S:
 //   potential  -3 (u.S.u) / (2 R^5) + T / (2 R^3)
 //   force      -3 S u / R^5 + (15 (u.S.u) / (2 R^7) - 3 T / (2 R^5)) u.
 #include "bh_device.h"
@@ -35,27 +35,24 @@ struct Member {
   double dx, dy, dz, dp;
 };
 
-// The quadrupole term of one cell entry (S, T from qpack) at relative
-// position (dx, dy, dz) with ri = 1/R.
-__device__ __forceinline__ void quad_term(Member &M, const float4 *__restrict__ qpack, int slot, float dx, float dy,
-                                          float dz, float ri) {
-  const float4 a = qpack[2 * (int64_t)slot], b = qpack[2 * (int64_t)slot + 1];
-  // a = (xx, yy, zz, xy), b = (xz, yz, trace, 0)
+// The quadrupole term of one cell entry at relative position (dx, dy, dz),
+// with R^2 = |u|^2 + eps^2 and ri = 1/R; a = 3 (xx, yy, zz, xy), b = (3 xz,
+// 3 yz, T, 1.5 T).  With S3 = 3 S and w = u.S3.u the terms above read
+//   force       r5 (2.5 w ri^2 - 1.5 T) u - r5 S3 u
+//   -potential  0.5 r5 (w - T R^2),        r5 = ri^5.
+__device__ __forceinline__ void quad_term(Member &M, const float4 a, const float4 b, float dx, float dy, float dz,
+                                          float R2, float ri) {
   const float sx = __builtin_fmaf(a.x, dx, __builtin_fmaf(a.w, dy, b.x * dz));
   const float sy = __builtin_fmaf(a.w, dx, __builtin_fmaf(a.y, dy, b.y * dz));
   const float sz = __builtin_fmaf(b.x, dx, __builtin_fmaf(b.y, dy, a.z * dz));
-  const float usu = __builtin_fmaf(dx, sx, __builtin_fmaf(dy, sy, dz * sz));
-  const float r2 = ri * ri;
-  const float r3 = ri * r2;
-  const float r5 = r3 * r2;
-  const float r7 = r5 * r2;
-  const float c = __builtin_fmaf(7.5f * usu, r7, -1.5f * b.z * r5);
-  const float k = -3.0f * r5;
-  M.ax = __builtin_fmaf(k, sx, __builtin_fmaf(c, dx, M.ax));
-  M.ay = __builtin_fmaf(k, sy, __builtin_fmaf(c, dy, M.ay));
-  M.az = __builtin_fmaf(k, sz, __builtin_fmaf(c, dz, M.az));
-  // pt accumulates -potential
-  M.pt = __builtin_fmaf(1.5f * usu, r5, __builtin_fmaf(-0.5f * b.z, r3, M.pt));
+  const float w = __builtin_fmaf(dx, sx, __builtin_fmaf(dy, sy, dz * sz));
+  const float ri2 = ri * ri;
+  const float r5 = ri2 * ri2 * ri;
+  const float c = r5 * __builtin_fmaf(2.5f * w, ri2, -b.w);
+  M.ax = __builtin_fmaf(-r5, sx, __builtin_fmaf(c, dx, M.ax));
+  M.ay = __builtin_fmaf(-r5, sy, __builtin_fmaf(c, dy, M.ay));
+  M.az = __builtin_fmaf(-r5, sz, __builtin_fmaf(c, dz, M.az));
+  M.pt = __builtin_fmaf(0.5f * r5, __builtin_fmaf(-b.z, R2, w), M.pt);
 }
 
 // U entries (value e, rounding residue l when NEAR) against this lane's
@@ -65,7 +62,20 @@ __device__ __forceinline__ void quad_term(Member &M, const float4 *__restrict__ 
 template <int U, bool NEAR, bool QUAD = false>
 __device__ __forceinline__ void terms(Member &M, const float4 (&e)[U], const float4 (&l)[U], float eps2,
                                       const int (&sl)[U], const float4 *__restrict__ qpack) {
-  float dx[U], dy[U], dz[U], q[U], mr[U], ri[U];
+  float dx[U], dy[U], dz[U], q[U], mr[U], ri[U], R2[U];
+  // the moments are fetched first (a particle's slot is clamped to 0 and its
+  // values unused), so that the monopole terms hide their latency
+  float4 qa[U], qb[U];
+  int slot[U];
+  if (QUAD) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      slot[u] = NEAR ? __float_as_int(l[u].w) : sl[u];
+      const int64_t at = 2 * (int64_t)max(slot[u], 0);
+      qa[u] = qpack[at];
+      qb[u] = qpack[at + 1];
+    }
+  }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     dx[u] = e[u].x - M.x;
@@ -86,6 +96,10 @@ __device__ __forceinline__ void terms(Member &M, const float4 (&e)[U], const flo
   for (int u = 0; u < U; ++u) q[u] = __builtin_fmaf(dy[u], dy[u], q[u]);
 #pragma unroll
   for (int u = 0; u < U; ++u) q[u] = __builtin_fmaf(dz[u], dz[u], q[u]);
+  if (QUAD) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) R2[u] = q[u];
+  }
 #pragma unroll
   for (int u = 0; u < U; ++u) q[u] = __builtin_amdgcn_rsqf(q[u]);  // 1/r
   if (QUAD) {
@@ -108,10 +122,8 @@ __device__ __forceinline__ void terms(Member &M, const float4 (&e)[U], const flo
   }
   if (QUAD) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int slot = NEAR ? __float_as_int(l[u].w) : sl[u];
-      if (slot >= 0) quad_term(M, qpack, slot, dx[u], dy[u], dz[u], ri[u]);
-    }
+    for (int u = 0; u < U; ++u)
+      if (slot[u] >= 0) quad_term(M, qa[u], qb[u], dx[u], dy[u], dz[u], R2[u], ri[u]);
   }
 }
 
@@ -123,7 +135,8 @@ __device__ __forceinline__ void fold(Member &M) {
   M.ax = M.ay = M.az = M.pt = 0.0f;
 }
 
-constexpr int kU = 8;  // entries per block of terms
+constexpr int kU = 8;      // entries per block of terms
+constexpr int kUQuad = 4;  // the same for the quadrupole sums (register pressure)
 
 // One chunk with R lane partitions: partition `part` takes entries part,
 // part + R, ...; R is a compile-time constant so that the four entries of a
@@ -133,22 +146,23 @@ template <bool NEAR, int R, bool QUAD>
 __device__ __forceinline__ void chunk_part(Member &M, const float4 *__restrict__ h, const float4 *__restrict__ l,
                                            const int *__restrict__ hs, const float4 *__restrict__ qpack, int n,
                                            int part, float eps2) {
+  constexpr int B = QUAD ? 2 : 4;  // entries per block (register pressure of the quadrupole terms)
   const int mine = (n - part + R - 1) / R;
   const float4 *ph = h + part;
   const float4 *pl = l + part;
   const int *ps = QUAD && !NEAR ? hs + part : nullptr;
   int t = 0;
-  for (; t + 4 <= mine; t += 4, ph += 4 * R, pl += 4 * R) {
-    float4 e4[4], r4[4];
-    int s4[4] = {-1, -1, -1, -1};
+  for (; t + B <= mine; t += B, ph += B * R, pl += B * R) {
+    float4 e4[B], r4[B];
+    int s4[B];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < B; ++u) {
       e4[u] = ph[u * R];
       r4[u] = NEAR ? pl[u * R] : e4[u];
-      if (QUAD && !NEAR) s4[u] = ps[u * R];
+      s4[u] = (QUAD && !NEAR) ? ps[u * R] : -1;
     }
-    if (QUAD && !NEAR) ps += 4 * R;
-    terms<4, NEAR, QUAD>(M, e4, r4, eps2, s4, qpack);
+    if (QUAD && !NEAR) ps += B * R;
+    terms<B, NEAR, QUAD>(M, e4, r4, eps2, s4, qpack);
   }
   for (; t < mine; ++t, ph += R, pl += R) {
     const float4 e1[1] = {ph[0]}, r1[1] = {NEAR ? pl[0] : ph[0]};
@@ -168,39 +182,40 @@ __device__ __forceinline__ void chunk_sum(Member &M, const float4 *__restrict__ 
                                           int n, int R, int part, float eps2, const int *__restrict__ hs = nullptr,
                                           const float4 *__restrict__ qpack = nullptr) {
   constexpr bool FS = QUAD && !NEAR;  // far slots to load
-  float4 e[kU], r[kU];
-  int sl[kU];
+  constexpr int KU = QUAD ? kUQuad : kU;  // entries per block
+  float4 e[KU], r[KU];
+  int sl[KU];
 #pragma unroll
-  for (int u = 0; u < kU; ++u) sl[u] = -1;
+  for (int u = 0; u < KU; ++u) sl[u] = -1;
   if (R == 1) {
     // every lane takes the same entries: scalar loads, scalar operands; the
     // next block is fetched while the current one is summed
     int t = 0;
-    if (n >= kU) {
+    if (n >= KU) {
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
+      for (int u = 0; u < KU; ++u) {
         e[u] = h[u];
         r[u] = NEAR ? l[u] : e[u];
         if (FS) sl[u] = hs[u];
       }
-      for (t = kU; t + kU <= n; t += kU) {
-        float4 ne[kU], nr[kU];
-        int ns[kU];
+      for (t = KU; t + KU <= n; t += KU) {
+        float4 ne[KU], nr[KU];
+        int ns[KU];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
+        for (int u = 0; u < KU; ++u) {
           ne[u] = h[t + u];
           nr[u] = NEAR ? l[t + u] : ne[u];
           ns[u] = FS ? hs[t + u] : -1;
         }
-        terms<kU, NEAR, QUAD>(M, e, r, eps2, sl, qpack);
+        terms<KU, NEAR, QUAD>(M, e, r, eps2, sl, qpack);
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
+        for (int u = 0; u < KU; ++u) {
           e[u] = ne[u];
           r[u] = nr[u];
           sl[u] = ns[u];
         }
       }
-      terms<kU, NEAR, QUAD>(M, e, r, eps2, sl, qpack);
+      terms<KU, NEAR, QUAD>(M, e, r, eps2, sl, qpack);
     }
     for (; t < n; ++t) {
       const float4 e1[1] = {h[t]}, r1[1] = {NEAR ? l[t] : h[t]};

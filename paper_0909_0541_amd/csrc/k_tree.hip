@@ -527,8 +527,11 @@ __global__ void k_moments(int lev, const int32_t *__restrict__ lcells, const int
     }
 #pragma unroll
     for (int k = 0; k < 6; ++k) qmom[6 * (int64_t)slot + k] = S[k];
-    qpack[2 * (int64_t)slot] = make_float4((float)S[0], (float)S[1], (float)S[2], (float)S[3]);
-    qpack[2 * (int64_t)slot + 1] = make_float4((float)S[4], (float)S[5], (float)(S[0] + S[1] + S[2]), 0.0f);
+    // as the force sum reads them: 3 S and the trace T (and 1.5 T)
+    const double T = S[0] + S[1] + S[2];
+    qpack[2 * (int64_t)slot] = make_float4((float)(3.0 * S[0]), (float)(3.0 * S[1]), (float)(3.0 * S[2]),
+                                           (float)(3.0 * S[3]));
+    qpack[2 * (int64_t)slot + 1] = make_float4((float)(3.0 * S[4]), (float)(3.0 * S[5]), (float)T, (float)(1.5 * T));
   }
   meta[slot] = (int8_t)(lev == kKeyLevels ? 32 * kBucket + lev : lev);
   }
