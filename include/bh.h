@@ -100,9 +100,14 @@ typedef struct {
                             stack to up to 16 new walk tasks, which waves with no group left
                             take in the same launch, so that long lists are walked and summed
                             by several waves; tasks 5 hand-overs deep walk to the end (0:
-                            default, 18 per particle of a walk wave, i.e. 18 n / (CUs x walk
-                            waves per CU), at least 12288; -1: never; else >= 64).  Results
-                            do not depend on when or where the tasks ran, only on the cap. */
+                            default, automatic: 48 per particle of a walk wave, i.e.
+                            48 n / (CUs x walk waves per CU), at least 12288, and at least 4
+                            times the mean list length of the previous force call on the
+                            context, so that only outlier walks split; -1: never; else
+                            >= 64, exactly).  Results do not depend on when or where the
+                            tasks ran, only on the cap (with the automatic cap, two calls on
+                            the same input agree bit for bit when their previous calls had
+                            lists of the same mean length). */
   int32_t quadrupole;    /* 1: builds also compute every cell's second mass moments S about its
                             centre of mass (bottom-up, parallel axes, FP64), and bh_compute_forces
                             and bh_compute_forces_batch add to each cell entry of a list the
@@ -192,8 +197,9 @@ bh_status bh_compute_forces(bh_ctx *ctx, double eps, double theta, const float *
 
 /* Same with per-system parameters: eps_sys, theta_sys host FP64 [n_systems].
  * A system's results equal, bit for bit, those of the same system run alone
- * with the same split-walk visit cap (the default cap grows with the total
- * particle count, so set bh_options.split_visits explicitly for that). */
+ * with the same split-walk visit cap (the automatic cap depends on the total
+ * particle count and the previous call, so give bh_options.split_visits a
+ * fixed value for that). */
 bh_status bh_compute_forces_batch(bh_ctx *ctx, const double *eps_sys, const double *theta_sys,
                                   const float *theta_group, float *acc, float *pot);
 

@@ -548,14 +548,22 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
   // split walks (long lists walked and summed by several waves)
   const int grid = c->num_cu * (c->opt.waves_per_cu > 0 ? c->opt.waves_per_cu : c->walk_bpc);
   const int fgrid = c->num_cu * (c->opt.waves_per_cu > 0 ? c->opt.waves_per_cu : (quad ? c->force_bpc_q : c->force_bpc));
-  // The default visit cap scales with the particles per walk wave (a walk
-  // that outlasts the average wave's share of the walk is the one to split;
-  // that share grows with the particles per wave), never below kSplitVisits.
+  // The automatic visit cap scales with the particles per walk wave (a walk
+  // that outlasts a multiple of the average wave's share is the one to
+  // split), never below kSplitVisits; in the walk it also grows to
+  // kSplitMeanFactor times the mean list length of the previous walk on this
+  // context, so that where every list is long (small theta) only the outliers
+  // split: splitting most groups costs more than it balances.
   const int64_t auto_cap = std::max<int64_t>(kSplitVisits, kSplitPerParticle * c->n / std::max(grid, 1));
+  const bool auto_split = c->opt.split_visits == 0;
   const int visit_cap = c->opt.split_visits < 0
                             ? 0
-                            : (c->opt.split_visits == 0 ? (int)std::min<int64_t>(auto_cap, INT32_MAX / 2)
-                                                        : c->opt.split_visits);
+                            : (auto_split ? (int)std::min<int64_t>(auto_cap, INT32_MAX / 2) : c->opt.split_visits);
+  if (!c->walk_hist.p) {
+    st = ensure(c, c->walk_hist, 4 * sizeof(int32_t), "walk history");
+    if (st) return st;
+    fill_i32(P<int32_t>(c->walk_hist), 0, 4, c->stream);
+  }
   if (c->seg_cap == 0) {
     c->task_cap = 4096;
     c->range_cap = 1 << 16;
@@ -610,6 +618,7 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
     W.seg_cap = c->seg_cap;
     W.gsplit = P<int32_t>(c->gsplit);
     W.visit_cap = visit_cap;
+    W.mean_list = auto_split ? P<int32_t>(c->walk_hist) : nullptr;
     W.wait_ticks = c->wait_ticks;
     reset_list_counters(P<DevInfo>(c->info), c->stream);
     split_reset(W.ctr, P<DevInfo>(c->info), W.tasks, c->task_cap, c->stream);
@@ -687,7 +696,7 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
   if (st) return st;
   force_items_device(P<int32_t>(c->ginfo), P<int32_t>(c->gsplit), P<int32_t>(c->gnseg), P<int32_t>(c->glist),
                      P<DevInfo>(c->info), (int64_t)gcap, P<int32_t>(c->item_n), P<int32_t>(c->item_off), P<int32_t>(c->items),
-                     c->scan_tmp.p, c->stream);
+                     c->scan_tmp.p, P<int32_t>(c->walk_hist), c->stream);
   ForceArgs F{};
   F.items = P<int32_t>(c->items);
   F.ginfo = P<int32_t>(c->ginfo);

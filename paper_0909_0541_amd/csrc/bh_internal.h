@@ -110,7 +110,8 @@ struct Segment {
 };
 constexpr int kSplitDepth = 5;       // tasks this many hand-overs deep walk to the end
 constexpr int kSplitVisits = 12288;  // smallest default node tests before a walk hands over
-constexpr int kSplitPerParticle = 18;  // default cap: this many node tests per particle of a walk wave
+constexpr int kSplitPerParticle = 48;  // default cap: this many node tests per particle of a walk wave
+constexpr int kSplitMeanFactor = 4;    // and at least this many times the previous walk's mean list length
 constexpr int kDonateTasks = 16;     // tasks made from one handed-over stack
 struct SplitCounters {               // device
   int32_t tasks;                     // task slots reserved
@@ -209,6 +210,7 @@ struct bh_ctx {
   bh::DevBuf mlp_feat;          // FP32 [n][12] features of bh_group_theta
   bh::DevBuf pp_next;           // int32 per slot: thread pointers of the per-particle walk
   bh::DevBuf order_hist;        // int32 cost bins of the queue orders
+  bh::DevBuf walk_hist;         // int32 [4]: mean list length of the last force call (automatic split cap)
   bh::DevBuf item_order;        // int32 queue position -> force item (longest first)
   // split walks: tasks (ping-pong), range pool, segments, counters, per-group
   // flags, segment sort and partial sums
@@ -327,6 +329,7 @@ struct WalkListArgs {
   int32_t *far_slot;         // nullable: node slot of each far entry (-1 a particle), for quadrupoles
   // split walks
   int visit_cap;             // node tests before a walk hands over its stack (0: never)
+  const int32_t *mean_list;  // nullable: previous mean list length; the cap is raised to kSplitMeanFactor x it
   SplitCounters *ctr;
   WalkTask *tasks;           // task slots (ctr->tasks reserved)
   int task_cap;
@@ -410,7 +413,7 @@ struct ForceArgs {
 };
 void force_items_device(const int32_t *ginfo, const int32_t *gsplit, const int32_t *gnseg, const int32_t *glist,
                         DevInfo *info, int64_t cap, int32_t *nblk, int32_t *off, int32_t *items, void *scan_tmp,
-                        hipStream_t s);
+                        int32_t *mean_list, hipStream_t s);
 void force_lists_device(const ForceArgs &a, int grid, hipStream_t s);
 void item_order_device(const ForceArgs &f, int64_t cap, int32_t *hist, int32_t *order, hipStream_t s);
 int force_lists_blocks_per_cu(bool quad);

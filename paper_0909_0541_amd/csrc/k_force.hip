@@ -393,11 +393,17 @@ __global__ __launch_bounds__(256) void k_item_counts(const int32_t *__restrict__
   }
 }
 
-// Items as (group, member block + 256 x (segment + 1) for a split group).
+// Items as (group, member block + 256 x (segment + 1) for a split group);
+// and the mean list length of this call, for the next walk's split cap.
 __global__ void k_item_fill(const int32_t *__restrict__ ginfo, const int32_t *__restrict__ gsplit,
                             const int32_t *__restrict__ gnseg, const int32_t *__restrict__ off,
-                            const DevInfo *__restrict__ info, int32_t *__restrict__ items) {
+                            const DevInfo *__restrict__ info, int32_t *__restrict__ items,
+                            int32_t *__restrict__ mean_list) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g == 0 && mean_list) {
+    const unsigned long long G = (unsigned long long)max(info->n_groups, 1);
+    mean_list[0] = (int32_t)min(info->list_entries / G, (unsigned long long)(INT32_MAX / 64));
+  }
   if (g >= info->n_groups) return;
   const int nb = (ginfo[3 * g + 1] + kWave - 1) / kWave;
   const int ns = gsplit[g] ? gnseg[g] : 0;
@@ -413,11 +419,11 @@ __global__ void k_item_fill(const int32_t *__restrict__ ginfo, const int32_t *__
 
 void force_items_device(const int32_t *ginfo, const int32_t *gsplit, const int32_t *gnseg, const int32_t *glist,
                         DevInfo *info, int64_t cap, int32_t *nblk, int32_t *off, int32_t *items, void *scan_tmp,
-                        hipStream_t s) {
+                        int32_t *mean_list, hipStream_t s) {
   const unsigned blocks = (unsigned)((cap + 255) / 256);
   k_item_counts<<<blocks, 256, 0, s>>>(ginfo, gsplit, gnseg, glist, info, cap, nblk);
   scan_exclusive_i32(nblk, off, cap, &info->n_items, scan_tmp, s);
-  k_item_fill<<<blocks, 256, 0, s>>>(ginfo, gsplit, gnseg, off, info, items);
+  k_item_fill<<<blocks, 256, 0, s>>>(ginfo, gsplit, gnseg, off, info, items, mean_list);
 }
 
 int force_lists_blocks_per_cu(bool quad) {

@@ -138,14 +138,16 @@ __device__ __forceinline__ int wait_slot(const WalkListArgs &a, int t, int lane)
 }
 
 // The next unit of a wave: its group, with task >= 0 when it is a task; a
-// negative group when the wave has no more work.  Tasks come first: a task
-// continues a long walk, which is on the critical path of the launch.  A
+// negative group when the wave has no more work.  A wave looks for tasks
+// once the group queues are empty (a look at the shared task counters before
+// every group would make every unit wait on a line that the units' own
+// counter keeps busy): a task continues a long walk, and the tasks run in
+// the tail of the launch, where the waves left have nothing else to do.  A
 // wave that sees a reserved slot no wave has claimed takes a ticket (the
-// next slot number); when the ticket's slot is not yet published the wave
-// walks groups meanwhile and looks at the slot again at the end of each
-// unit, so the claim never blocks while groups are left.  When no group is
-// left, the wave waits for its ticket's slot (taking a ticket if it has
-// none): the waiting waves form a queue in slot order.  Groups are taken in
+// next slot number); a ticket whose slot is not yet published is looked at
+// again at the end of each unit.  When no group is left, the wave waits for
+// its ticket's slot (taking a ticket if it has none): the waiting waves form
+// a queue in slot order.  Groups are taken in
 // Morton order from eight contiguous eighths, one per XCD (workgroups go to
 // the XCDs round robin), so that the waves sharing an L2 walk neighbouring
 // groups and read mostly the same nodes; a wave whose eighth is done takes
@@ -157,7 +159,7 @@ __device__ __forceinline__ int next_unit(const WalkListArgs &a, int G, int xcd, 
   for (;;) {
     int rc = -1;
     if (a.visit_cap > 0) {
-      if (ticket < 0) {
+      if (ticket < 0 && tried >= 8) {
         const int head = __builtin_amdgcn_readfirstlane(
             __hip_atomic_load(&a.ctr->queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         const int res = __builtin_amdgcn_readfirstlane(
@@ -231,6 +233,10 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
   const int lane = lane_id();
   const int G = a.info->n_groups;
   const int nslots = a.nsys + a.info->n_slots;
+  // the automatic cap also stays above a multiple of the last mean list
+  int visit_cap = a.visit_cap;
+  if (visit_cap > 0 && a.mean_list)
+    visit_cap = max(visit_cap, kSplitMeanFactor * min(__builtin_amdgcn_readfirstlane(a.mean_list[0]), INT32_MAX / 64));
 
   const int xcd = blockIdx.x & 7;
   int tried = 0, ticket = -1;
@@ -289,7 +295,7 @@ __global__ __launch_bounds__(kWave) void k_walk_lists(WalkListArgs a) {
       }
     }
     // units at the deepest level walk to the end
-    int cap = (a.visit_cap > 0 && key_depth(key) < kSplitDepth) ? a.visit_cap : 0;
+    int cap = (visit_cap > 0 && key_depth(key) < kSplitDepth) ? visit_cap : 0;
     wave_sync();
     int visits = 0;
     // Software pipeline: the records of the next batch are loaded while the

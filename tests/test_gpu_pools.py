@@ -24,7 +24,8 @@ def test_pools_grow_and_walk_again(gpu):
     ps, ms = inputs.plummer(2000, 3, with_vel=False)[:2]
     pos, mass = inputs.clustered(200000, 21, n_halos=50)[:2]
     eps, theta, n_crit = 1e-4, 0.3, 64
-    c = bh.Context()
+    # (a fixed cap: the automatic one may change with the previous call's lists)
+    c = bh.Context(split_visits=-1)
     c.build_tree(to_dev(ps), to_dev(ms))
     c.make_groups(n_crit)
     c.compute_forces(1e-3, 0.5)

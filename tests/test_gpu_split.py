@@ -23,7 +23,7 @@ def _cases():
 
 
 @pytest.mark.parametrize("case", _cases(), ids=lambda c: c[0])
-@pytest.mark.parametrize("cap", [64, 500])
+@pytest.mark.parametrize("cap", [64, 500, 0])
 def test_split_lists_and_forces_match_oracle(gpu, case, cap):
     bh = gpu
     name, pos, mass, eps, theta, n_crit = case
