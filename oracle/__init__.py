@@ -13,6 +13,8 @@ functions:
   Tree.group_list(g, theta)               -- one group's interaction list
   Tree.second_moments()                   -- per-node second mass moments
   Tree.forces(..., quadrupole=True)       -- the same sums with quadrupole terms
+  neighbors(pos, mass, h, lists=False)    -- brute-force neighbours and SPH density
+  sph_kernel(r, h)                        -- the cubic spline kernel
 """
 from __future__ import annotations
 
@@ -59,6 +61,10 @@ def lib():
         L.oracle_tree_nodes.restype = None
         L.oracle_tree_group_info.argtypes = [vp, vp, vp, vp, vp]
         L.oracle_tree_group_info.restype = None
+        L.oracle_sph_kernel.argtypes = [dbl, dbl]
+        L.oracle_sph_kernel.restype = dbl
+        L.oracle_neighbors.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]
+        L.oracle_neighbors.restype = C.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = C.c_int
         _lib = L
@@ -217,6 +223,36 @@ class Tree:
         node = np.zeros(L, dtype=np.int64)
         lib().oracle_tree_group_list(self._h, int(g), float(theta), L, _p(xyzm), _p(part), _p(node))
         return xyzm, part, node
+
+
+def sph_kernel(r: float, h: float) -> float:
+    """The cubic spline kernel W(r, h) with compact support h."""
+    return lib().oracle_sph_kernel(float(r), float(h))
+
+
+def neighbors(pos, mass, h, lists: bool = False):
+    """Brute-force neighbours within each particle's own radius h_i (j != i,
+    |x_j - x_i| < h_i): dict with count [n] (int64), rho [n] (SPH density,
+    when mass is given) and, with lists, a list of index arrays (increasing)."""
+    pos = _f64(pos).reshape(-1, 3)
+    n = pos.shape[0]
+    h = np.ascontiguousarray(np.broadcast_to(np.asarray(h, dtype=np.float64), (n,)))
+    m = None if mass is None else _f64(mass)
+    count = np.zeros(n, dtype=np.int64)
+    rho = None if m is None else np.zeros(n)
+    if lib().oracle_neighbors(n, _p(pos), _p(m), _p(h), _p(count), _p(rho), None, None) != 0:
+        raise ValueError("oracle_neighbors failed")
+    out = {"count": count, "rho": rho}
+    if lists:
+        off = np.zeros(n + 1, dtype=np.int64)
+        off[1:] = np.cumsum(count)
+        nbr = np.zeros(max(int(off[-1]), 1), dtype=np.int64)
+        if lib().oracle_neighbors(n, _p(pos), None, _p(h), None, None, _p(off), _p(nbr)) != 0:
+            raise ValueError("oracle_neighbors failed")
+        out["lists"] = [nbr[off[i]:off[i + 1]] for i in range(n)]
+        out["offsets"] = off
+        out["flat"] = nbr[:off[-1]]
+    return out
 
 
 def tree_forces(pos, mass, eps: float, theta: float, n_crit: int, theta_g=None):

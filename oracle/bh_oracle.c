@@ -28,6 +28,7 @@
  * Everything is FP64, compiled without floating-point contraction, evaluated
  * in the order written.  The recursion follows Fig. "treewalk" directly.
  */
+#define _GNU_SOURCE
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -672,6 +673,56 @@ void oracle_tree_group_info(void *h, int64_t *first, int64_t *count, double *lo,
       if (hi) hi[3 * g + k] = t->ghi[3 * g + k];
     }
   }
+}
+
+/* ---- neighbour search (the general treewalk of Sec. 3.2 applied to short-
+ * range interactions, as in SPH) ------------------------------------------
+ *
+ * The plain definition, by brute force over all pairs: the neighbours of
+ * particle i are the particles j != i with |x_j - x_i| < h_i (its own search
+ * radius, the "gather" form), the distance squared evaluated as
+ * (dx*dx + dy*dy) + dz*dz with dx = x_j - x_i.  The SPH density
+ *   rho_i = m_i W(0, h_i) + sum over neighbours m_j W(|x_j - x_i|, h_i)
+ * uses the cubic spline kernel of Monaghan and Lattanzio (1985) with compact
+ * support h: q = r/h, W = 8/(pi h^3) (1 - 6 q^2 + 6 q^3) for q < 1/2,
+ * 16/(pi h^3) (1 - q)^3 for q < 1, 0 beyond (a choice: the paper names SPH
+ * as the application without fixing a kernel). */
+double oracle_sph_kernel(double r, double h) {
+  const double q = r / h;
+  const double sigma = 8.0 / (M_PI * h * h * h);
+  if (q < 0.5) return sigma * (1.0 - 6.0 * q * q + 6.0 * q * q * q);
+  if (q < 1.0) {
+    const double u = 1.0 - q;
+    return sigma * 2.0 * u * u * u;
+  }
+  return 0.0;
+}
+
+/* count[i] (nullable), rho[i] (nullable) and, when offsets is given, the
+ * neighbours of i (input indices, increasing) at nbr[offsets[i] ...]. */
+int oracle_neighbors(int64_t n, const double *pos, const double *mass, const double *h, int64_t *count,
+                     double *rho, const int64_t *offsets, int64_t *nbr) {
+  if (n < 0 || (n > 0 && (!pos || !h))) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < n; ++i) {
+    const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+    const double hi = h[i];
+    const double h2 = hi * hi;
+    int64_t c = 0;
+    double r = mass ? mass[i] * oracle_sph_kernel(0.0, hi) : 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      const double dx = pos[3 * j] - xi, dy = pos[3 * j + 1] - yi, dz = pos[3 * j + 2] - zi;
+      const double r2 = (dx * dx + dy * dy) + dz * dz;
+      if (!(r2 < h2)) continue;
+      if (offsets && nbr) nbr[offsets[i] + c] = j;
+      ++c;
+      if (mass) r += mass[j] * oracle_sph_kernel(sqrt(r2), hi);
+    }
+    if (count) count[i] = c;
+    if (rho) rho[i] = r;
+  }
+  return 0;
 }
 
 int oracle_num_threads(void) {
