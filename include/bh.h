@@ -90,7 +90,10 @@ typedef struct {
   int32_t n_walk_attempts; /* last force call: walks run (more than 1 when a list pool had to grow) */
   double t_particle_ms;     /* per-particle walk calls (thread pointers, walk and sum) */
   int32_t n_particle_calls;
-  int32_t pad;
+  int32_t n_neighbor_calls;
+  double t_neighbor_ms;     /* bh_neighbors calls */
+  int64_t neighbor_pairs;   /* last bh_neighbors: neighbours found (sum of the counts) */
+  int64_t neighbor_tests;   /* last bh_neighbors: member-candidate pairs whose distance was tested */
 } bh_stats;
 
 typedef struct {
@@ -358,6 +361,27 @@ bh_status bh_export_sorted(bh_ctx *ctx, uint64_t *keys, int32_t *perm);
  * children; reals device FP64 [slots][6] = mass, centre of mass x, y, z, side
  * l (+inf for buckets), s.  Slot k < n_systems is the root of system k. */
 bh_status bh_export_nodes(bh_ctx *ctx, int32_t *ints, double *reals);
+
+/* ---- neighbour search (SPH) ------------------------------------------- */
+
+/* The general treewalk of Sec. 3.2 (Fig. "general_treewalk") applied to a
+ * short-range interaction, on the current tree and groups (bh_make_groups
+ * first).  The neighbours of particle i are the particles j != i of the same
+ * tree with |x_j - x_i| < h_i (each particle's own radius: the "gather"
+ * form), the squared distance (dx^2 + dy^2) + dz^2 evaluated in FP64 as
+ * written.  h: device FP64 [n], input order, positive and finite (else
+ * BH_EINVAL at the next synchronising call).  Outputs, device, input order,
+ * each nullable (at least one): count int32 [n], the neighbour counts; rho
+ * FP64 [n], the SPH density m_i W(0, h_i) + sum over neighbours m_j W(r_ij,
+ * h_i) with the cubic spline kernel of compact support h (W = 8/(pi h^3)
+ * (1 - 6q^2 + 6q^3) for q = r/h < 1/2, 16/(pi h^3) (1 - q)^3 for q < 1);
+ * offsets int64 [n + 1] with nbr int32 [offsets[n]]: the input indices of
+ * i's neighbours at nbr[offsets[i] ...], in no particular order (offsets
+ * from an exclusive scan of an earlier call's counts; a mismatch is reported
+ * as BH_EINVAL).  Systems of a batch are searched separately.  Asynchronous;
+ * stats report the pairs found and tested. */
+bh_status bh_neighbors(bh_ctx *ctx, const double *h, int32_t *count, double *rho, const int64_t *offsets,
+                       int32_t *nbr);
 
 /* Second mass moments of every slot about its centre of mass (tree built
  * with the quadrupole option, else BH_ESTATE): moments device FP64

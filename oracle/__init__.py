@@ -65,6 +65,8 @@ def lib():
         L.oracle_sph_kernel.restype = dbl
         L.oracle_neighbors.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]
         L.oracle_neighbors.restype = C.c_int
+        L.oracle_neighbors_sel.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp]
+        L.oracle_neighbors_sel.restype = C.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = C.c_int
         _lib = L
@@ -253,6 +255,21 @@ def neighbors(pos, mass, h, lists: bool = False):
         out["offsets"] = off
         out["flat"] = nbr[:off[-1]]
     return out
+
+
+def neighbors_sampled(pos, mass, h, sel):
+    """Brute-force neighbour counts and SPH density of the particles sel only
+    (each against all n): dict with count [k] and rho [k] (or None)."""
+    pos = _f64(pos).reshape(-1, 3)
+    n = pos.shape[0]
+    h = np.ascontiguousarray(np.broadcast_to(np.asarray(h, dtype=np.float64), (n,)))
+    m = None if mass is None else _f64(mass)
+    sel = np.ascontiguousarray(sel, dtype=np.int64)
+    count = np.zeros(sel.shape[0], dtype=np.int64)
+    rho = None if m is None else np.zeros(sel.shape[0])
+    if lib().oracle_neighbors_sel(n, _p(pos), _p(m), _p(h), sel.shape[0], _p(sel), _p(count), _p(rho)) != 0:
+        raise ValueError("oracle_neighbors_sel failed")
+    return {"count": count, "rho": rho}
 
 
 def tree_forces(pos, mass, eps: float, theta: float, n_crit: int, theta_g=None):

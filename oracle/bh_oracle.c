@@ -725,6 +725,35 @@ int oracle_neighbors(int64_t n, const double *pos, const double *mass, const dou
   return 0;
 }
 
+/* The same for the selected particles sel[0 .. nsel) only (count, rho in
+ * selection order), by brute force over all n. */
+int oracle_neighbors_sel(int64_t n, const double *pos, const double *mass, const double *h, int64_t nsel,
+                         const int64_t *sel, int64_t *count, double *rho) {
+  if (n < 0 || nsel < 0 || (nsel > 0 && (!pos || !h || !sel))) return -1;
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(| : bad)
+  for (int64_t k = 0; k < nsel; ++k) {
+    const int64_t i = sel[k];
+    if (i < 0 || i >= n) { bad |= 1; continue; }
+    const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+    const double hi = h[i];
+    const double h2 = hi * hi;
+    int64_t c = 0;
+    double r = mass ? mass[i] * oracle_sph_kernel(0.0, hi) : 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      const double dx = pos[3 * j] - xi, dy = pos[3 * j + 1] - yi, dz = pos[3 * j + 2] - zi;
+      const double r2 = (dx * dx + dy * dy) + dz * dz;
+      if (!(r2 < h2)) continue;
+      ++c;
+      if (mass) r += mass[j] * oracle_sph_kernel(sqrt(r2), hi);
+    }
+    if (count) count[k] = c;
+    if (rho) rho[k] = r;
+  }
+  return bad ? -1 : 0;
+}
+
 int oracle_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -40,7 +40,8 @@ class _Stats(C.Structure):
                 ("n_groups_calls", C.c_int32), ("n_walk_calls", C.c_int32), ("n_force_calls", C.c_int32),
                 ("n_split_groups", C.c_int32), ("n_segments", C.c_int32), ("n_split_levels", C.c_int32),
                 ("n_walk_attempts", C.c_int32), ("t_particle_ms", C.c_double), ("n_particle_calls", C.c_int32),
-                ("pad", C.c_int32)]
+                ("n_neighbor_calls", C.c_int32), ("t_neighbor_ms", C.c_double), ("neighbor_pairs", C.c_int64),
+                ("neighbor_tests", C.c_int64)]
 
 
 class _Mlp(C.Structure):
@@ -95,6 +96,7 @@ def load():
         "bh_export_sorted": ([vp, vp, vp], C.c_int),
         "bh_export_nodes": ([vp, vp, vp], C.c_int),
         "bh_export_moments": ([vp, vp], C.c_int),
+        "bh_neighbors": ([vp, vp, vp, vp, vp, vp], C.c_int),
         "bh_export_groups": ([vp, vp, vp, vp, vp], C.c_int),
     }
     for name, (args, res) in sigs.items():
@@ -148,7 +150,10 @@ class Stats:
     n_walk_attempts: int
     t_particle_ms: float
     n_particle_calls: int
-    pad: int
+    n_neighbor_calls: int
+    t_neighbor_ms: float
+    neighbor_pairs: int
+    neighbor_tests: int
 
 
 class Context:
@@ -456,6 +461,35 @@ class Context:
         reals = torch.empty((st.n_slots, 6), dtype=torch.float64, device=dev)
         self._check(self._L.bh_export_nodes(self._h, _ptr(ints), _ptr(reals)))
         return ints, reals
+
+    def neighbors(self, h: torch.Tensor, count: bool = True, rho: bool = False, offsets: torch.Tensor | None = None,
+                  nbr: torch.Tensor | None = None):
+        """Neighbour search on the current tree and groups: h FP64 [n] device
+        (input order).  Returns (count int32 [n] or None, rho FP64 [n] or
+        None); with offsets (int64 [n + 1]) and nbr (int32 [offsets[n]]) the
+        lists are written into nbr."""
+        n = self.n
+        dev = torch.device("cuda", torch.cuda.current_device())
+        _dev(h, torch.float64, (n,), "h")
+        c = torch.empty(n, dtype=torch.int32, device=dev) if count else None
+        r = torch.empty(n, dtype=torch.float64, device=dev) if rho else None
+        if offsets is not None:
+            _dev(offsets, torch.int64, (n + 1,), "offsets")
+            _dev(nbr, torch.int32, None, "nbr")
+        self._check(self._L.bh_neighbors(self._h, _ptr(h), _ptr(c), _ptr(r), _ptr(offsets), _ptr(nbr)))
+        return c, r
+
+    def neighbor_lists(self, h: torch.Tensor):
+        """Counts, then CSR lists: (offsets int64 [n + 1], nbr int32 [total]),
+        each row in walk order."""
+        c, _ = self.neighbors(h, count=True)
+        n = self.n
+        off = torch.zeros(n + 1, dtype=torch.int64, device=c.device)
+        off[1:] = torch.cumsum(c.to(torch.int64), 0)
+        total = int(off[-1].item())
+        nbr = torch.empty(max(total, 1), dtype=torch.int32, device=c.device)
+        self.neighbors(h, count=False, rho=False, offsets=off, nbr=nbr)
+        return off, nbr[:total]
 
     def export_moments(self):
         """Second mass moments about each node's centre of mass, FP64

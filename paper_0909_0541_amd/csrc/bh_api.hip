@@ -259,6 +259,8 @@ static bh_status check_device_errors(bh_ctx *c) {
   if (e & kErrStack) return fail(c, BH_EINTERNAL, "walk stack capacity exceeded or node range corrupt");
   if (e & kErrPool) return fail(c, BH_EINTERNAL, "interaction list pool exhausted");
   if (e & kErrWait) return fail(c, BH_EINTERNAL, "walk task wait timed out");
+  if (e & kErrRadius) return fail(c, BH_EINVAL, "search radius h must be positive and finite");
+  if (e & kErrListSpace) return fail(c, BH_EINVAL, "neighbour list offsets do not match the neighbour counts");
   return BH_OK;
 }
 
@@ -341,6 +343,7 @@ static bh_status build_common(bh_ctx *c, int32_t nsys, const int64_t *offsets, c
   if (st) return st;
   c->have_tree = true;
   c->have_quad = quad;
+  c->have_neighbors = false;
   return BH_OK;
 }
 
@@ -393,7 +396,8 @@ void bh_destroy(bh_ctx *c) {
                     &c->glists, &c->far_pool, &c->near_pool, &c->far_next, &c->near_next,
                     &c->items, &c->item_n, &c->item_off, &c->feps, &c->mlp_work, &c->mlp_feat, &c->pp_next, &c->order_hist, &c->item_order, &c->tasks, &c->ranges, &c->segs,
                     &c->split_ctr, &c->gsplit, &c->gnseg, &c->gsegfirst, &c->skeys[0], &c->skeys[1], &c->svals[0],
-                    &c->svals[1], &c->shist, &c->sscan, &c->srows, &c->spbase, &c->sgroups, &c->psum};
+                    &c->svals[1], &c->shist, &c->sscan, &c->srows, &c->spbase, &c->sgroups, &c->psum,
+                    &c->qmom, &c->qpack, &c->far_slot, &c->walk_hist};
   for (DevBuf *b : bufs) free_buf(*b);
   if (c->graph) (void)hipGraphExecDestroy(c->graph);
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
@@ -401,7 +405,7 @@ void bh_destroy(bh_ctx *c) {
   if (c->stage) (void)hipHostFree(c->stage);
   if (c->split_host) (void)hipHostFree(c->split_host);
   if (c->stage_event) (void)hipEventDestroy(c->stage_event);
-  Timer *ts[] = {&c->t_build, &c->t_groups, &c->t_walk, &c->t_force, &c->t_particle};
+  Timer *ts[] = {&c->t_build, &c->t_groups, &c->t_walk, &c->t_force, &c->t_particle, &c->t_neighbor};
   for (Timer *t : ts)
     for (hipEvent_t e : t->ev) (void)hipEventDestroy(e);
   delete c;
@@ -909,6 +913,11 @@ bh_status bh_get_stats(bh_ctx *c, bh_stats *out) {
   out->t_walk_ms = timer_take(c->t_walk, &out->n_walk_calls);
   out->t_force_ms = timer_take(c->t_force, &out->n_force_calls);
   out->t_particle_ms = timer_take(c->t_particle, &out->n_particle_calls);
+  out->t_neighbor_ms = timer_take(c->t_neighbor, &out->n_neighbor_calls);
+  if (c->have_neighbors) {
+    out->neighbor_pairs = (int64_t)d.nb_pairs;
+    out->neighbor_tests = (int64_t)d.nb_tests;
+  }
   return st;
 }
 
@@ -1116,6 +1125,41 @@ bh_status bh_export_nodes(bh_ctx *c, int32_t *ints, double *reals) {
   k_export_nodes<<<blocks_for(cap), 256, 0, c->stream>>>(P<NodeRec>(c->nodes), P<int8_t>(c->meta),
                                                           P<DevInfo>(c->info), c->nsys, ints, reals);
   return hip_check(c, hipGetLastError(), "kernel launch (export nodes)");
+}
+
+bh_status bh_neighbors(bh_ctx *c, const double *h, int32_t *count, double *rho, const int64_t *offsets,
+                       int32_t *nbr) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (!c->have_tree) return fail(c, BH_ESTATE, "neighbour search requested before a tree was built");
+  if (!c->have_groups) return fail(c, BH_ESTATE, "neighbour search requested before bh_make_groups");
+  if (c->n > 0 && !h) return fail(c, BH_EINVAL, "h must not be NULL");
+  if ((offsets == nullptr) != (nbr == nullptr)) return fail(c, BH_EINVAL, "offsets and nbr go together");
+  if (!count && !rho && !nbr) return fail(c, BH_EINVAL, "no output requested");
+  c->have_neighbors = true;
+  if (c->n == 0) return BH_OK;
+  if (!c->nb_bpc) c->nb_bpc = neighbors_blocks_per_cu();
+  const int grid = c->num_cu * (c->opt.waves_per_cu > 0 ? c->opt.waves_per_cu : c->nb_bpc);
+  NeighborArgs A{};
+  A.nodes = P<NodeRec>(c->nodes);
+  A.ginfo = P<int32_t>(c->ginfo);
+  A.gbox = P<double>(c->gbox);
+  A.spos = P<double>(c->spos);
+  A.smass = P<double>(c->smass);
+  A.perm = P<int32_t>(c->perm);
+  A.info = P<DevInfo>(c->info);
+  A.nsys = c->nsys;
+  A.h = h;
+  A.count = count;
+  A.rho = rho;
+  A.offsets = offsets;
+  A.nbr = nbr;
+  bh_status st = timer_start(c, c->t_neighbor);
+  if (st) return st;
+  neighbors_device(A, grid, c->stream);
+  st = timer_stop(c, c->t_neighbor);
+  if (st) return st;
+  return hip_check(c, hipGetLastError(), "kernel launch (neighbours)");
 }
 
 bh_status bh_export_moments(bh_ctx *c, double *moments) {

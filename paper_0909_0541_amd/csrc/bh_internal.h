@@ -62,6 +62,8 @@ struct DevInfo {
   unsigned long long list_entries;
   int32_t max_list;
   int32_t n_items;        // force work items (group, member block)
+  unsigned long long nb_pairs;  // neighbour search: neighbours found (sum of the counts)
+  unsigned long long nb_tests;  // neighbour search: candidate pairs whose distance was tested
   // Counters that every wave of a kernel updates, each in a 128-byte line of
   // its own (atomics on one line serialise behind each other).
   alignas(128) int32_t queue2;  // force work queue head
@@ -87,6 +89,8 @@ enum : int32_t {
   kErrBuild = 16,
   kErrPool = 32,
   kErrWait = 64,
+  kErrRadius = 128,      // neighbour search: a radius not positive and finite
+  kErrListSpace = 256,   // neighbour search: offsets leave a list too little or too much room
 };
 
 // Split walks: a walk that has tested split_visits nodes hands its remaining
@@ -145,7 +149,7 @@ struct bh_ctx {
   int num_cu = 0;
   std::string err;
   bh_options opt{0, 0, 0, 0};
-  int walk_bpc = 0, force_bpc = 0, force_bpc_q = 0, probe_bpc = 0;  // resident blocks per CU of the persistent kernels
+  int walk_bpc = 0, force_bpc = 0, force_bpc_q = 0, probe_bpc = 0, nb_bpc = 0;  // resident blocks per CU of the persistent kernels
 
   // current tree
   int64_t n = 0;
@@ -154,6 +158,7 @@ struct bh_ctx {
   bool have_groups = false;
   bool have_forces = false;
   bool have_quad = false;  // the current tree carries second moments
+  bool have_neighbors = false;  // a neighbour search ran since the last build
   bool capturing = false;         // recording a step into a HIP graph: no uploads, syncs or timers
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t graph = nullptr; // the captured step
@@ -230,7 +235,7 @@ struct bh_ctx {
   bool stage_event_used = false;
   uint64_t *sorted_keys = nullptr;    // the key buffer holding the sorted keys
 
-  bh::Timer t_build, t_groups, t_walk, t_force, t_particle;
+  bh::Timer t_build, t_groups, t_walk, t_force, t_particle, t_neighbor;
 };
 
 namespace bh {
@@ -341,6 +346,23 @@ struct WalkListArgs {
   int32_t *gsplit;           // per group: 1 when its list is in segments
 };
 void walk_lists_device(const WalkListArgs &a, int grid, hipStream_t s);
+// k_neighbors.hip: neighbour search and SPH density over the groups
+struct NeighborArgs {
+  const NodeRec *nodes;
+  const int32_t *ginfo;
+  const double *gbox;
+  const double *spos, *smass;
+  const int32_t *perm;
+  DevInfo *info;
+  int nsys;
+  const double *h;        // [n] input order
+  int32_t *count;         // nullable, [n] input order
+  double *rho;            // nullable
+  const int64_t *offsets; // nullable, [n + 1]: lists are written when set
+  int32_t *nbr;
+};
+void neighbors_device(const NeighborArgs &a, int grid, hipStream_t s);
+int neighbors_blocks_per_cu();
 // k_particle.hip: the per-particle walk and sum (no shared lists)
 void particle_forces_device(const NodeRec *nodes, int nslots, int nsys, const SysInfo *sys, const SysParam *par,
                             const double *spos, const int32_t *perm, int64_t n, int32_t *nxt, float *acc,

@@ -1,0 +1,274 @@
+// Neighbour search and SPH density: the general treewalk of Sec. 3.2 (Fig.
+// "general_treewalk") applied to a short-range interaction, as in smoothed
+// particle hydrodynamics, the application the paper names.
+//
+// The neighbours of particle i are the particles j != i with |x_j - x_i| <
+// h_i, its own search radius (the "gather" form).  The walk is the group form
+// used for gravity: one wavefront per group, persistent grid pulling groups
+// from an atomic queue, up to 64 nodes tested per iteration from a stack of
+// slot ranges in LDS.  The distance test of the general walk prunes a cell
+// whose particles all lie farther than the group's largest radius from the
+// group's bounding box: every particle of a cell lies within
+// (sqrt(3)/2) l + s of its centre of mass (l the cube side, s the distance of
+// the centre of mass from the cube's centre).  A particle leaf inside the
+// box grown by that radius is a candidate; candidates collect in LDS and are
+// tested against every member, one member per lane, in FP64 with the
+// squared distance (dx^2 + dy^2) + dz^2 rounded as written, so the decision
+// r^2 < h_i^2 is the same as a plain CPU evaluation.  The pruning bounds
+// carry margins far above FP64 rounding; they only skip work, the per-pair
+// test decides.
+//
+// The SPH density sums m_j W(r_ij, h_i) over the neighbours, plus the
+// particle's own m_i W(0, h_i), with the cubic spline kernel of Monaghan and
+// Lattanzio with compact support h (the paper fixes no kernel).  Lists, when
+// asked for, hold the input indices of the neighbours in walk order.
+#include "bh_device.h"
+
+namespace bh {
+
+namespace {
+
+constexpr int kNbStack = 1024;                   // range stack entries
+constexpr int kNbReserve = 8 * 24;               // growth bound in one-range mode
+constexpr int kNbCand = 512;                     // candidate buffer
+constexpr int kNbBlocks = BH_MAX_NCRIT / kWave;  // member blocks of the largest group
+constexpr double kHalfSqrt3 = 0.86602540378443865;
+
+__device__ __forceinline__ void wave_sync() { __syncthreads(); }
+
+__device__ __forceinline__ double sph_w(double r, double h) {
+  const double q = r / h;
+  const double sigma = 8.0 / (3.14159265358979323846 * h * h * h);
+  if (q < 0.5) return sigma * (1.0 - 6.0 * q * q + 6.0 * q * q * q);
+  if (q < 1.0) {
+    const double u = 1.0 - q;
+    return sigma * 2.0 * u * u * u;
+  }
+  return 0.0;
+}
+
+__global__ void k_nb_reset(DevInfo *info) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    info->queue = 0;
+    info->nb_pairs = 0;
+    info->nb_tests = 0;
+  }
+}
+
+// Tests the ncand candidates in cand[] against every member block.
+__device__ __forceinline__ void flush(const NeighborArgs &a, const int *cand, int ncand, int gf, int gc, int nb,
+                                      int lane, const double (&hb)[kNbBlocks], int (&cb)[kNbBlocks],
+                                      double (&rb)[kNbBlocks], const int64_t (&ob)[kNbBlocks],
+                                      const int64_t (&lb)[kNbBlocks], unsigned long long &tests) {
+#pragma unroll
+  for (int b = 0; b < kNbBlocks; ++b) {
+    if (b < nb) {
+      const int i = gf + b * kWave + lane;
+      const bool live = i < gf + gc;
+      double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+      if (live) {
+        x0 = a.spos[3 * (int64_t)i];
+        x1 = a.spos[3 * (int64_t)i + 1];
+        x2 = a.spos[3 * (int64_t)i + 2];
+      }
+      const double h = hb[b];
+      const double h2 = __dmul_rn(h, h);
+      int c = cb[b];
+      double r = rb[b];
+      for (int k = 0; k < ncand; ++k) {
+        const int j = cand[k];
+        const double dx = __dsub_rn(a.spos[3 * (int64_t)j], x0);
+        const double dy = __dsub_rn(a.spos[3 * (int64_t)j + 1], x1);
+        const double dz = __dsub_rn(a.spos[3 * (int64_t)j + 2], x2);
+        const double r2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+        if (live && j != i && r2 < h2) {
+          if (a.rho) r = __dadd_rn(r, __dmul_rn(a.smass[j], sph_w(sqrt(r2), h)));
+          if (a.nbr && c < lb[b]) a.nbr[ob[b] + c] = a.perm[j];
+          ++c;
+        }
+      }
+      if (live) tests += (unsigned long long)ncand;
+      cb[b] = c;
+      rb[b] = r;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kWave) void k_neighbors(NeighborArgs a) {
+  __shared__ int2 stk[kNbStack];
+  __shared__ int cand[kNbCand];
+  __shared__ int mark[kWave];
+  const int lane = lane_id();
+  const int G = a.info->n_groups;
+  const int nslots = a.nsys + a.info->n_slots;
+  unsigned long long pairs = 0, tests = 0;
+  for (;;) {
+    const int g = take_one(&a.info->queue, lane);
+    if (g >= G) break;
+    const int gf = a.ginfo[3 * g], gc = a.ginfo[3 * g + 1], gs = a.ginfo[3 * g + 2];
+    const int nb = min((gc + kWave - 1) / kWave, kNbBlocks);
+    if ((gc + kWave - 1) / kWave > kNbBlocks || gs < 0 || gs >= a.nsys) {
+      if (lane == 0) atomicOr(&a.info->err, kErrStack);
+      continue;
+    }
+    // members: radii, the group's largest, output offsets
+    double hb[kNbBlocks], rb[kNbBlocks];
+    int cb[kNbBlocks];
+    int64_t ob[kNbBlocks], lb[kNbBlocks];
+    double hmax = 0.0;
+    bool bad = false;
+#pragma unroll
+    for (int b = 0; b < kNbBlocks; ++b) {
+      const int i = gf + b * kWave + lane;
+      const bool live = b < nb && i < gf + gc;
+      const int o = live ? a.perm[i] : 0;
+      hb[b] = live ? a.h[o] : 1.0;
+      if (live && !(hb[b] > 0.0 && hb[b] < INFINITY)) bad = true;
+      if (live) hmax = fmax(hmax, hb[b]);
+      cb[b] = 0;
+      rb[b] = 0.0;
+      ob[b] = 0;
+      lb[b] = 0;
+      if (live && a.offsets) {
+        ob[b] = a.offsets[o];
+        lb[b] = a.offsets[o + 1] - ob[b];
+      }
+    }
+    if (__ballot(bad)) {
+      if (lane == 0) atomicOr(&a.info->err, kErrRadius);
+      continue;
+    }
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) hmax = fmax(hmax, shfl_xor_d(hmax, d));
+    // the group's box grown by the largest radius, with a margin above the
+    // rounding of these sums
+    double elo[3], ehi[3], cpad = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double lo = a.gbox[6 * (int64_t)g + k], hi = a.gbox[6 * (int64_t)g + 3 + k];
+      const double pad = hmax * (1.0 + 1e-9) + 1e-15 * fmax(fabs(lo), fabs(hi));
+      elo[k] = lo - pad;
+      ehi[k] = hi + pad;
+      cpad += 1e-15 * fmax(fabs(lo), fabs(hi));
+    }
+
+    int sp = 1, ncand = 0;
+    if (lane == 0) stk[0] = make_int2(gs, 1);
+    wave_sync();
+    int budget = 4 * nslots + 4;
+    while (sp > 0) {
+      if (--budget < 0) {
+        if (lane == 0) atomicOr(&a.info->err, kErrStack);
+        break;
+      }
+      // take up to 64 nodes from the top ranges (one range while the stack
+      // is high: then the walk is depth first and the stack stays bounded)
+      const bool starved = sp > kNbStack - kWave - kNbReserve;
+      const int nread = starved ? 1 : min(sp, kWave);
+      int2 e = make_int2(0, 0);
+      if (lane < nread) e = stk[sp - 1 - lane];
+      const int cnt = (lane < nread) ? e.y : 0;
+      const int pre = wave_inclusive_sum(cnt);
+      const int total = __shfl(pre, nread - 1, kWave);
+      const int take = min(starved ? 8 : kWave, total);
+      const int start = pre - cnt;
+      const int kfull = __popcll(__ballot(lane < nread && pre <= take));
+      mark[lane] = -1;
+      wave_sync();
+      if (lane < nread && start < take) mark[start] = lane;
+      wave_sync();
+      const int ei = wave_inclusive_max(mark[lane]);
+      const int e_start = __shfl(start, ei < 0 ? 0 : ei, kWave);
+      const int e_first = __shfl(e.x, ei < 0 ? 0 : ei, kWave);
+      if (kfull < nread) {
+        const int pstart = __shfl(start, kfull, kWave);
+        if (pstart < take && lane == kfull)
+          stk[sp - 1 - kfull] = make_int2(e.x + (take - pstart), e.y - (take - pstart));
+      }
+      sp -= kfull;
+      const int node = e_first + (lane - e_start);
+      if (__ballot(lane < take && (node < 0 || node >= nslots))) {
+        if (lane == 0) atomicOr(&a.info->err, kErrStack);
+        break;
+      }
+      bool push = false, is_cand = false;
+      int2 rng = make_int2(0, 0);
+      int j = 0;
+      if (lane < take) {
+        const NodeRec r = a.nodes[node];
+        double d2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const double ek = fmax(0.0, fmax(elo[k] - r.com[k], r.com[k] - ehi[k]));
+          d2 += ek * ek;
+        }
+        if (r.child < 0) {
+          is_cand = r.count > 0 && d2 == 0.0;  // a particle inside the grown box
+          j = r.first;
+        } else {
+          // every particle of the cell lies within R of its centre of mass
+          const double R = (kHalfSqrt3 * r.l + r.s) * (1.0 + 1e-9) + cpad;
+          push = !(d2 > R * R);
+          rng = make_int2(r.child, r.nchild);
+        }
+      }
+      const unsigned long long pm = __ballot(push), cm = __ballot(is_cand);
+      const int npush = __popcll(pm), nc = __popcll(cm);
+      wave_sync();
+      if (sp + npush > kNbStack) {
+        if (lane == 0) atomicOr(&a.info->err, kErrStack);
+        break;
+      }
+      if (push) stk[sp + rank_below(pm)] = rng;
+      if (is_cand) cand[ncand + rank_below(cm)] = j;
+      sp += npush;
+      ncand += nc;
+      wave_sync();
+      if (ncand > kNbCand - kWave) {
+        flush(a, cand, ncand, gf, gc, nb, lane, hb, cb, rb, ob, lb, tests);
+        ncand = 0;
+        wave_sync();
+      }
+    }
+    flush(a, cand, ncand, gf, gc, nb, lane, hb, cb, rb, ob, lb, tests);
+    wave_sync();
+    // outputs in input order
+    bool short_list = false;
+#pragma unroll
+    for (int b = 0; b < kNbBlocks; ++b) {
+      const int i = gf + b * kWave + lane;
+      if (b < nb && i < gf + gc) {
+        const int o = a.perm[i];
+        if (a.count) a.count[o] = cb[b];
+        if (a.rho) a.rho[o] = __dadd_rn(__dmul_rn(a.smass[i], sph_w(0.0, hb[b])), rb[b]);
+        if (a.offsets && (int64_t)cb[b] != lb[b]) short_list = true;
+        pairs += (unsigned long long)cb[b];
+      }
+    }
+    if (__ballot(short_list) && lane == 0) atomicOr(&a.info->err, kErrListSpace);
+  }
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    pairs += __shfl_xor(pairs, d, kWave);
+    tests += __shfl_xor(tests, d, kWave);
+  }
+  if (lane == 0 && (pairs || tests)) {
+    atomicAdd(&a.info->nb_pairs, pairs);
+    atomicAdd(&a.info->nb_tests, tests);
+  }
+}
+
+}  // namespace
+
+int neighbors_blocks_per_cu() {
+  int b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_neighbors, kWave, 0) != hipSuccess || b < 1) b = 8;
+  return b;
+}
+
+void neighbors_device(const NeighborArgs &a, int grid, hipStream_t s) {
+  k_nb_reset<<<1, 64, 0, s>>>(a.info);
+  k_neighbors<<<(unsigned)grid, kWave, 0, s>>>(a);
+}
+
+}  // namespace bh

@@ -79,3 +79,13 @@ def test_two_particles():
         assert list(out["count"]) == [n, n]
         w0, wd = oracle.sph_kernel(0.0, hh), oracle.sph_kernel(d, hh)
         np.testing.assert_allclose(out["rho"], [m[0] * w0 + n * m[1] * wd, m[1] * w0 + n * m[0] * wd], rtol=1e-14)
+
+
+def test_sampled_equals_full():
+    pos, mass = inputs.clustered(3000, 5, n_halos=6)[:2]
+    h = 0.03 * np.random.default_rng(1).uniform(0.5, 1.5, 3000)
+    full = oracle.neighbors(pos, mass, h)
+    sel = np.array([0, 17, 1234, 2999])
+    part = oracle.neighbors_sampled(pos, mass, h, sel)
+    assert np.array_equal(part["count"], full["count"][sel])
+    assert np.array_equal(part["rho"], full["rho"][sel])
