@@ -13,7 +13,8 @@ Prints one JSON line.  value = tree-force interactions per second of whole
 steps at that theta (sum over members of list length - 1, divided by the
 step time).  Beside it: particles/s; the learned per-group theta at the same
 error (its output shift bisected the same way, features + network in the
-step); the quadrupole option at the same error; the per-particle walk at the
+step); the quadrupole option at the same error; the neighbour search with SPH
+densities at 64 neighbours per particle; the per-particle walk at the
 same error; the workload's own theta of 0.6; the roofline of the dominant kernel
 (the force sum, FP32 VALU); and the FP64 CPU oracle's throughput.
 """
@@ -83,6 +84,7 @@ def parse():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-particle", action="store_true", help="skip the per-particle walk A/B leg")
     ap.add_argument("--no-quadrupole", action="store_true", help="skip the quadrupole A/B leg")
+    ap.add_argument("--no-neighbors", action="store_true", help="skip the neighbour-search leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-systems leg")
     ap.add_argument("--copy-check-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the timed steps, "
@@ -254,6 +256,59 @@ def quadrupole_leg(args, judge, dpos, dmass, w, line, inter_mono):
             "step": "tree build with second moments, groups, list walk, force sum with quadrupole terms"}
 
 
+FP64_VALU_PEAK_TFLOPS = 78.6    # MI355X published FP64 vector peak
+NEIGHBOR_NCRIT = 64             # group size of the neighbour search
+FLOPS_PER_NEIGHBOR_TEST = 8      # FP64: 3 sub, 3 mul, 2 add for r^2 (the compare is not counted)
+
+
+def neighbor_leg(args, dpos, dmass, w):
+    """Neighbour search and SPH density (the general treewalk for a short-
+    range interaction) on the same particles: radii for 64 neighbours (set-up,
+    a few count passes), then the search with counts and densities timed."""
+    import torch
+
+    from paper_0909_0541_amd import bh, sph
+
+    n = dpos.shape[0]
+    c = bh.Context(timing=True, waves_per_cu=args.waves_per_cu)
+    c.build_tree(dpos, dmass)
+    c.make_groups(w.n_crit)
+    h = sph.smoothing_lengths(c, dpos, n_target=64)
+    # the search's own groups: smaller groups test fewer candidate pairs per
+    # member (64 measured best on this box; 256 tests 2.2x as many pairs)
+    c.make_groups(NEIGHBOR_NCRIT)
+    cnt = torch.empty(n, dtype=torch.int32, device="cuda")
+    rho = torch.empty(n, dtype=torch.float64, device="cuda")
+    for _ in range(max(args.warmup, 1)):
+        c.neighbors(h, count=True, rho=True)
+    torch.cuda.synchronize()
+    c.get_stats()
+    steps = max(1, args.steps)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        c.neighbors(h, count=True, rho=True)
+    e1.record()
+    torch.cuda.synchronize()
+    st = c.get_stats()
+    if st.error_flags:
+        raise RuntimeError(f"device error flags {st.error_flags}")
+    ms = e0.elapsed_time(e1) / steps
+    kms = st.t_neighbor_ms / max(st.n_neighbor_calls, 1)
+    achieved = FLOPS_PER_NEIGHBOR_TEST * st.neighbor_tests / (kms * 1e-3) / 1e12
+    cn = c.neighbors(h, count=True)[0].cpu()
+    return {"workload": w.name, "n": n, "n_target": 64, "n_crit": NEIGHBOR_NCRIT, "ms_per_call": ms, "kernel_ms": kms,
+            "neighbor_pairs": st.neighbor_pairs, "pair_tests": st.neighbor_tests,
+            "pairs_per_s": st.neighbor_pairs / (ms * 1e-3), "tests_per_s": st.neighbor_tests / (ms * 1e-3),
+            "particles_per_s": n / (ms * 1e-3),
+            "median_neighbors": float(cn.median().item()), "max_neighbors": int(cn.max().item()),
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / FP64_VALU_PEAK_TFLOPS, "kernel": "k_neighbors",
+                         "flops_per_test": FLOPS_PER_NEIGHBOR_TEST},
+            "step": "neighbour counts and SPH densities of every particle on a built tree and groups"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -390,6 +445,8 @@ def main():
             "force_kernel_tflops": FLOPS_PER_INTERACTION * st2.interactions / (s2["force"] * 1e-3) / 1e12}
     if calib is not None and not args.no_quadrupole:
         line["quadrupole"] = quadrupole_leg(args, judge, dpos, dmass, w, line, inter)
+    if not args.no_neighbors:
+        line["neighbors"] = neighbor_leg(args, dpos, dmass, w)
     if calib is not None and not args.no_particle:
         line["per_particle"] = particle_leg(args, ctx, judge, dpos, dmass, w, line)
     if not args.no_batch:

@@ -1138,8 +1138,9 @@ bh_status bh_neighbors(bh_ctx *c, const double *h, int32_t *count, double *rho, 
   if (!count && !rho && !nbr) return fail(c, BH_EINVAL, "no output requested");
   c->have_neighbors = true;
   if (c->n == 0) return BH_OK;
-  if (!c->nb_bpc) c->nb_bpc = neighbors_blocks_per_cu();
-  const int grid = c->num_cu * (c->opt.waves_per_cu > 0 ? c->opt.waves_per_cu : c->nb_bpc);
+  const int variant = c->n_crit <= 64 ? 0 : (c->n_crit <= 128 ? 1 : 2);
+  if (!c->nb_bpc[variant]) c->nb_bpc[variant] = neighbors_blocks_per_cu(c->n_crit);
+  const int grid = c->num_cu * (c->opt.waves_per_cu > 0 ? c->opt.waves_per_cu : c->nb_bpc[variant]);
   NeighborArgs A{};
   A.nodes = P<NodeRec>(c->nodes);
   A.ginfo = P<int32_t>(c->ginfo);
@@ -1156,7 +1157,7 @@ bh_status bh_neighbors(bh_ctx *c, const double *h, int32_t *count, double *rho, 
   A.nbr = nbr;
   bh_status st = timer_start(c, c->t_neighbor);
   if (st) return st;
-  neighbors_device(A, grid, c->stream);
+  neighbors_device(A, c->n_crit, grid, c->stream);
   st = timer_stop(c, c->t_neighbor);
   if (st) return st;
   return hip_check(c, hipGetLastError(), "kernel launch (neighbours)");

@@ -149,7 +149,7 @@ struct bh_ctx {
   int num_cu = 0;
   std::string err;
   bh_options opt{0, 0, 0, 0};
-  int walk_bpc = 0, force_bpc = 0, force_bpc_q = 0, probe_bpc = 0, nb_bpc = 0;  // resident blocks per CU of the persistent kernels
+  int walk_bpc = 0, force_bpc = 0, force_bpc_q = 0, probe_bpc = 0, nb_bpc[3] = {0, 0, 0};  // resident blocks per CU of the persistent kernels
 
   // current tree
   int64_t n = 0;
@@ -361,8 +361,8 @@ struct NeighborArgs {
   const int64_t *offsets; // nullable, [n + 1]: lists are written when set
   int32_t *nbr;
 };
-void neighbors_device(const NeighborArgs &a, int grid, hipStream_t s);
-int neighbors_blocks_per_cu();
+void neighbors_device(const NeighborArgs &a, int n_crit, int grid, hipStream_t s);
+int neighbors_blocks_per_cu(int n_crit);
 // k_particle.hip: the per-particle walk and sum (no shared lists)
 void particle_forces_device(const NodeRec *nodes, int nslots, int nsys, const SysInfo *sys, const SysParam *par,
                             const double *spos, const int32_t *perm, int64_t n, int32_t *nxt, float *acc,

@@ -14,7 +14,9 @@
 // box grown by that radius is a candidate; candidates collect in LDS and are
 // tested against every member, one member per lane, in FP64 with the
 // squared distance (dx^2 + dy^2) + dz^2 rounded as written, so the decision
-// r^2 < h_i^2 is the same as a plain CPU evaluation.  The pruning bounds
+// r^2 < h_i^2 is the same as a plain CPU evaluation.  A candidate's index,
+// position and mass go to LDS from the node record its lane just read, so
+// the member loop reads them as LDS broadcasts.  The pruning bounds
 // carry margins far above FP64 rounding; they only skip work, the per-pair
 // test decides.
 //
@@ -28,10 +30,9 @@ namespace bh {
 
 namespace {
 
-constexpr int kNbStack = 1024;                   // range stack entries
+constexpr int kNbStack = 512;                    // range stack entries
 constexpr int kNbReserve = 8 * 24;               // growth bound in one-range mode
-constexpr int kNbCand = 512;                     // candidate buffer
-constexpr int kNbBlocks = BH_MAX_NCRIT / kWave;  // member blocks of the largest group
+constexpr int kNbCand = 128;                     // candidate buffer
 constexpr double kHalfSqrt3 = 0.86602540378443865;
 
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }
@@ -55,8 +56,34 @@ __global__ void k_nb_reset(DevInfo *info) {
   }
 }
 
-// Tests the ncand candidates in cand[] against every member block.
-__device__ __forceinline__ void flush(const NeighborArgs &a, const int *cand, int ncand, int gf, int gc, int nb,
+// Candidates staged in LDS: sorted index, position and mass (taken from the
+// particle's node record by the lane that accepted it).
+struct alignas(16) CandRec {
+  double x, y, z, m;
+};
+struct Cand {
+  CandRec c[kNbCand];
+  int j[kNbCand];
+};
+
+// One member against one staged candidate.
+__device__ __forceinline__ void test_pair(const NeighborArgs &a, const CandRec &q, int j, int i, bool live, double x0,
+                                          double x1, double x2, double h, double h2, int64_t ob, int64_t lb, int &c,
+                                          double &r) {
+  const double dx = __dsub_rn(q.x, x0);
+  const double dy = __dsub_rn(q.y, x1);
+  const double dz = __dsub_rn(q.z, x2);
+  const double r2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+  if (live && j != i && r2 < h2) {
+    if (a.rho) r = __dadd_rn(r, __dmul_rn(q.m, sph_w(sqrt(r2), h)));
+    if (a.nbr && c < lb) a.nbr[ob + c] = a.perm[j];
+    ++c;
+  }
+}
+
+// Tests the ncand staged candidates against every member block.
+template <int kNbBlocks>
+__device__ __forceinline__ void flush(const NeighborArgs &a, const Cand &cd, int ncand, int gf, int gc, int nb,
                                       int lane, const double (&hb)[kNbBlocks], int (&cb)[kNbBlocks],
                                       double (&rb)[kNbBlocks], const int64_t (&ob)[kNbBlocks],
                                       const int64_t (&lb)[kNbBlocks], unsigned long long &tests) {
@@ -75,18 +102,7 @@ __device__ __forceinline__ void flush(const NeighborArgs &a, const int *cand, in
       const double h2 = __dmul_rn(h, h);
       int c = cb[b];
       double r = rb[b];
-      for (int k = 0; k < ncand; ++k) {
-        const int j = cand[k];
-        const double dx = __dsub_rn(a.spos[3 * (int64_t)j], x0);
-        const double dy = __dsub_rn(a.spos[3 * (int64_t)j + 1], x1);
-        const double dz = __dsub_rn(a.spos[3 * (int64_t)j + 2], x2);
-        const double r2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
-        if (live && j != i && r2 < h2) {
-          if (a.rho) r = __dadd_rn(r, __dmul_rn(a.smass[j], sph_w(sqrt(r2), h)));
-          if (a.nbr && c < lb[b]) a.nbr[ob[b] + c] = a.perm[j];
-          ++c;
-        }
-      }
+      for (int k = 0; k < ncand; ++k) test_pair(a, cd.c[k], cd.j[k], i, live, x0, x1, x2, h, h2, ob[b], lb[b], c, r);
       if (live) tests += (unsigned long long)ncand;
       cb[b] = c;
       rb[b] = r;
@@ -94,9 +110,13 @@ __device__ __forceinline__ void flush(const NeighborArgs &a, const int *cand, in
   }
 }
 
+// kNbBlocks: member blocks of 64 held per lane (the largest group / 64),
+// chosen by the host from the grouping so that small groups keep registers
+// free.
+template <int kNbBlocks>
 __global__ __launch_bounds__(kWave) void k_neighbors(NeighborArgs a) {
   __shared__ int2 stk[kNbStack];
-  __shared__ int cand[kNbCand];
+  __shared__ Cand cd;
   __shared__ int mark[kWave];
   const int lane = lane_id();
   const int G = a.info->n_groups;
@@ -194,6 +214,7 @@ __global__ __launch_bounds__(kWave) void k_neighbors(NeighborArgs a) {
       bool push = false, is_cand = false;
       int2 rng = make_int2(0, 0);
       int j = 0;
+      double px = 0.0, py = 0.0, pz = 0.0, pm = 0.0;
       if (lane < take) {
         const NodeRec r = a.nodes[node];
         double d2 = 0.0;
@@ -205,6 +226,10 @@ __global__ __launch_bounds__(kWave) void k_neighbors(NeighborArgs a) {
         if (r.child < 0) {
           is_cand = r.count > 0 && d2 == 0.0;  // a particle inside the grown box
           j = r.first;
+          px = r.com[0];
+          py = r.com[1];
+          pz = r.com[2];
+          pm = r.m;
         } else {
           // every particle of the cell lies within R of its centre of mass
           const double R = (kHalfSqrt3 * r.l + r.s) * (1.0 + 1e-9) + cpad;
@@ -212,25 +237,29 @@ __global__ __launch_bounds__(kWave) void k_neighbors(NeighborArgs a) {
           rng = make_int2(r.child, r.nchild);
         }
       }
-      const unsigned long long pm = __ballot(push), cm = __ballot(is_cand);
-      const int npush = __popcll(pm), nc = __popcll(cm);
+      const unsigned long long pmask = __ballot(push), cm = __ballot(is_cand);
+      const int npush = __popcll(pmask), nc = __popcll(cm);
       wave_sync();
       if (sp + npush > kNbStack) {
         if (lane == 0) atomicOr(&a.info->err, kErrStack);
         break;
       }
-      if (push) stk[sp + rank_below(pm)] = rng;
-      if (is_cand) cand[ncand + rank_below(cm)] = j;
+      if (push) stk[sp + rank_below(pmask)] = rng;
+      if (is_cand) {
+        const int q = ncand + rank_below(cm);
+        cd.j[q] = j;
+        cd.c[q] = CandRec{px, py, pz, pm};
+      }
       sp += npush;
       ncand += nc;
       wave_sync();
       if (ncand > kNbCand - kWave) {
-        flush(a, cand, ncand, gf, gc, nb, lane, hb, cb, rb, ob, lb, tests);
+        flush<kNbBlocks>(a, cd, ncand, gf, gc, nb, lane, hb, cb, rb, ob, lb, tests);
         ncand = 0;
         wave_sync();
       }
     }
-    flush(a, cand, ncand, gf, gc, nb, lane, hb, cb, rb, ob, lb, tests);
+    flush<kNbBlocks>(a, cd, ncand, gf, gc, nb, lane, hb, cb, rb, ob, lb, tests);
     wave_sync();
     // outputs in input order
     bool short_list = false;
@@ -260,15 +289,21 @@ __global__ __launch_bounds__(kWave) void k_neighbors(NeighborArgs a) {
 
 }  // namespace
 
-int neighbors_blocks_per_cu() {
+int neighbors_blocks_per_cu(int n_crit) {
   int b = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_neighbors, kWave, 0) != hipSuccess || b < 1) b = 8;
+  hipError_t e;
+  if (n_crit <= kWave) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_neighbors<1>, kWave, 0);
+  else if (n_crit <= 2 * kWave) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_neighbors<2>, kWave, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_neighbors<BH_MAX_NCRIT / kWave>, kWave, 0);
+  if (e != hipSuccess || b < 1) b = 8;
   return b;
 }
 
-void neighbors_device(const NeighborArgs &a, int grid, hipStream_t s) {
+void neighbors_device(const NeighborArgs &a, int n_crit, int grid, hipStream_t s) {
   k_nb_reset<<<1, 64, 0, s>>>(a.info);
-  k_neighbors<<<(unsigned)grid, kWave, 0, s>>>(a);
+  if (n_crit <= kWave) k_neighbors<1><<<(unsigned)grid, kWave, 0, s>>>(a);
+  else if (n_crit <= 2 * kWave) k_neighbors<2><<<(unsigned)grid, kWave, 0, s>>>(a);
+  else k_neighbors<BH_MAX_NCRIT / kWave><<<(unsigned)grid, kWave, 0, s>>>(a);
 }
 
 }  // namespace bh
