@@ -6,7 +6,9 @@ leg may import this package.  It loads ``oracle/liboracle.so`` (built from
 functions:
 
   direct(pos, mass, eps, idx=None)        -- Eq. (1) by direct summation
-  Tree(pos, mass)                         -- oct-tree of Sec. 3.1 in Morton order
+  Tree(pos, mass, curve=0)                -- oct-tree of Sec. 3.1 in Morton (0) or
+                                             Peano-Hilbert (1) order
+  hilbert_key(x, y, z)                    -- Peano-Hilbert index of a cell
   Tree.groups(n_crit)                     -- particle groups
   Tree.forces(eps, theta, theta_g=None, groups=None)
                                           -- grouped tree walk + Eq. (1) sums
@@ -39,6 +41,10 @@ def lib():
         L.oracle_direct.restype = C.c_int
         L.oracle_tree_build.argtypes = [i64, vp, vp]
         L.oracle_tree_build.restype = vp
+        L.oracle_tree_build2.argtypes = [i64, vp, vp, C.c_int]
+        L.oracle_tree_build2.restype = vp
+        L.oracle_hilbert_key.argtypes = [i64, i64, i64]
+        L.oracle_hilbert_key.restype = C.c_uint64
         L.oracle_tree_free.argtypes = [vp]
         L.oracle_tree_free.restype = None
         L.oracle_tree_groups.argtypes = [vp, C.c_int]
@@ -114,11 +120,12 @@ KIND_CELL, KIND_PARTICLE, KIND_BUCKET = 0, 1, 2
 class Tree:
     """The oracle's oct-tree over (pos, mass); see bh_oracle.c."""
 
-    def __init__(self, pos, mass):
+    def __init__(self, pos, mass, curve: int = 0):
+        """curve 0: Morton order; 1: Peano-Hilbert order."""
         self.pos = _f64(pos, (-1, 3))
         self.mass = _f64(mass)
         self.n = self.pos.shape[0]
-        h = lib().oracle_tree_build(self.n, _p(self.pos), _p(self.mass))
+        h = lib().oracle_tree_build2(self.n, _p(self.pos), _p(self.mass), int(curve))
         if not h:
             raise ValueError("oracle_tree_build rejected the input")
         self._h = h
@@ -225,6 +232,11 @@ class Tree:
         node = np.zeros(L, dtype=np.int64)
         lib().oracle_tree_group_list(self._h, int(g), float(theta), L, _p(xyzm), _p(part), _p(node))
         return xyzm, part, node
+
+
+def hilbert_key(x: int, y: int, z: int) -> int:
+    """Peano-Hilbert index of integer cell coordinates (21 bits per axis)."""
+    return int(lib().oracle_hilbert_key(int(x), int(y), int(z)))
 
 
 def sph_kernel(r: float, h: float) -> float:

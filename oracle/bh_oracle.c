@@ -103,7 +103,8 @@ typedef struct {
 typedef struct {
   int64_t n;
   double lo[3], side, scale;
-  uint64_t *key;        /* sorted Morton keys */
+  uint64_t *key;        /* sorted keys (Morton or Peano-Hilbert) */
+  int64_t *q;           /* integer cell coordinates [n][3], sorted order */
   int64_t *perm;        /* perm[k] = input index of the k-th particle in Morton order */
   double *spos, *smass; /* positions and masses in Morton order */
   orc_node *node;
@@ -125,6 +126,40 @@ static uint64_t morton_key(const int64_t q[3]) {
         (uint64_t)((q[2] >> b) & 1);
   }
   return k;
+}
+
+/* Peano-Hilbert index of a cell, by J. Skilling's method ("Programming the
+ * Hilbert curve", AIP Conf. Proc. 707, 2004): the coordinates are turned in
+ * place into the "transpose" of the index -- walking the bits from the top,
+ * each lower bit field is either inverted in x (when the current bit of an
+ * axis is set) or exchanged between x and that axis, then the result is
+ * Gray-decoded across the axes -- and the transpose's bits, read level by
+ * level with x first, are the index.  The curve starts at the origin cell and
+ * moves by one cell along one axis at every step; each octant of a cell is a
+ * contiguous range of indices, so the index's octal digits name the octree's
+ * cells as Morton digits do. */
+static uint64_t hilbert_key(const int64_t q[3]) {
+  uint32_t x[3] = {(uint32_t)q[0], (uint32_t)q[1], (uint32_t)q[2]};
+  for (uint32_t bit = 1u << (ORC_KEY_LEVELS - 1); bit > 1; bit >>= 1) {
+    const uint32_t low = bit - 1;
+    for (int a = 0; a < 3; ++a) {
+      if (x[a] & bit) {
+        x[0] ^= low;
+      } else {
+        const uint32_t swap = (x[0] ^ x[a]) & low;
+        x[0] ^= swap;
+        x[a] ^= swap;
+      }
+    }
+  }
+  x[1] ^= x[0];
+  x[2] ^= x[1];
+  uint32_t flip = 0;
+  for (uint32_t bit = 1u << (ORC_KEY_LEVELS - 1); bit > 1; bit >>= 1)
+    if (x[2] & bit) flip ^= bit - 1;
+  int64_t t[3];
+  for (int a = 0; a < 3; ++a) t[a] = (int64_t)(x[a] ^ flip);
+  return morton_key(t);
 }
 
 /* Octant (0..7) of a key at a given level (level 1 = first split of the root). */
@@ -224,7 +259,9 @@ static int64_t build_rec(orc_tree *t, int level, int64_t first, int64_t count, c
     int d = key_digit(t->key[p], level + 1);
     int64_t q = p;
     while (q < end && key_digit(t->key[q], level + 1) == d) ++q;
-    int64_t sub[3] = {2 * cell[0] + ((d >> 2) & 1), 2 * cell[1] + ((d >> 1) & 1), 2 * cell[2] + (d & 1)};
+    /* the sub-cell from a member's own cell coordinates (for either curve) */
+    const int sh = ORC_KEY_LEVELS - (level + 1);
+    int64_t sub[3] = {t->q[3 * p] >> sh, t->q[3 * p + 1] >> sh, t->q[3 * p + 2] >> sh};
     int64_t c = build_rec(t, level + 1, p, q - p, sub, id);
     if (c < 0) return -1;
     kids[nchild++] = c;
@@ -247,13 +284,14 @@ static int64_t build_rec(orc_tree *t, int level, int64_t first, int64_t count, c
 void oracle_tree_free(void *h) {
   orc_tree *t = (orc_tree *)h;
   if (!t) return;
-  free(t->key); free(t->perm); free(t->spos); free(t->smass); free(t->node);
+  free(t->key); free(t->q); free(t->perm); free(t->spos); free(t->smass); free(t->node);
   free(t->gfirst); free(t->gcount); free(t->glo); free(t->ghi);
   free(t);
 }
 
-/* Root cube, Morton keys, sort and recursive build.  Returns NULL on bad input. */
-void *oracle_tree_build(int64_t n, const double *pos, const double *mass) {
+/* Root cube, keys (curve 0: Morton, 1: Peano-Hilbert), sort and recursive
+ * build.  Returns NULL on bad input. */
+void *oracle_tree_build2(int64_t n, const double *pos, const double *mass, int curve) {
   if (n < 0) return NULL;
   orc_tree *t = (orc_tree *)calloc(1, sizeof(orc_tree));
   if (!t) return NULL;
@@ -284,11 +322,18 @@ void *oracle_tree_build(int64_t n, const double *pos, const double *mass) {
 
   /* integer cell coordinates at the finest level and their Morton keys */
   uint64_t *rawkey = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+  int64_t *rawq = (int64_t *)malloc((size_t)n * 3 * sizeof(int64_t));
   t->key = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+  t->q = (int64_t *)malloc((size_t)n * 3 * sizeof(int64_t));
   t->perm = (int64_t *)malloc((size_t)n * sizeof(int64_t));
   t->spos = (double *)malloc((size_t)n * 3 * sizeof(double));
   t->smass = (double *)malloc((size_t)n * sizeof(double));
-  if (!rawkey || !t->key || !t->perm || !t->spos || !t->smass) { free(rawkey); oracle_tree_free(t); return NULL; }
+  if (!rawkey || !rawq || !t->key || !t->q || !t->perm || !t->spos || !t->smass) {
+    free(rawkey);
+    free(rawq);
+    oracle_tree_free(t);
+    return NULL;
+  }
   for (int64_t i = 0; i < n; ++i) {
     int64_t q[3];
     for (int k = 0; k < 3; ++k) {
@@ -300,7 +345,8 @@ void *oracle_tree_build(int64_t n, const double *pos, const double *mass) {
       else c = (int64_t)floor(u);
       q[k] = c;
     }
-    rawkey[i] = morton_key(q);
+    rawkey[i] = curve ? hilbert_key(q) : morton_key(q);
+    for (int k = 0; k < 3; ++k) rawq[3 * i + k] = q[k];
     t->perm[i] = i;
   }
   /* Morton order, ties kept in input order */
@@ -310,15 +356,29 @@ void *oracle_tree_build(int64_t n, const double *pos, const double *mass) {
   for (int64_t i = 0; i < n; ++i) {
     int64_t j = t->perm[i];
     t->key[i] = rawkey[j];
-    for (int k = 0; k < 3; ++k) t->spos[3 * i + k] = pos[3 * j + k];
+    for (int k = 0; k < 3; ++k) {
+      t->spos[3 * i + k] = pos[3 * j + k];
+      t->q[3 * i + k] = rawq[3 * j + k];
+    }
     t->smass[i] = mass[j];
   }
   free(rawkey);
+  free(rawq);
 
   int64_t root_cell[3] = {0, 0, 0};
   t->root = build_rec(t, 0, 0, n, root_cell, -1);
   if (t->root < 0) { oracle_tree_free(t); return NULL; }
   return t;
+}
+
+void *oracle_tree_build(int64_t n, const double *pos, const double *mass) {
+  return oracle_tree_build2(n, pos, mass, 0);
+}
+
+/* The Peano-Hilbert index of integer cell coordinates q[0..3) (for pins). */
+uint64_t oracle_hilbert_key(int64_t x, int64_t y, int64_t z) {
+  const int64_t q[3] = {x, y, z};
+  return hilbert_key(q);
 }
 
 /* ------------------------------------------------------------------------- */
