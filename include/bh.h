@@ -13,7 +13,7 @@
  *   Eq. (2)/(3) modified opening criterion: a cell of side l whose centre of
  *              mass lies s from its geometric centre is far enough when
  *              d^2 > (l/theta + s)^2.
- *   Sec. 3.5   Morton ordering of the particles.
+ *   Sec. 3.5   Morton ordering of the particles (Peano-Hilbert as an option).
  *   Sec. 1, 3.2 the grouped (vectorised) walk: each group of nearby particles
  *              walks the tree once to build one interaction list that all its
  *              members sum over.  For a group, d is the distance from the
@@ -120,6 +120,11 @@ typedef struct {
                             monopole sums of Eq. 1: same lists, same opening test).  Force calls
                             then need a tree built with the option set (else BH_ESTATE); the
                             per-particle walk rejects it (BH_EINVAL).  0 (default): monopoles. */
+  int32_t curve;         /* order of the keys, the particles and the children of a cell (Sec. 3.5
+                            uses Morton order; Peano-Hilbert is the alternative it names):
+                            0 (default) Morton, bit interleaving; 1 Peano-Hilbert, consecutive
+                            cells face-adjacent.  The cells are the same either way; the order,
+                            and hence the groups, differ.  Takes effect at the next build. */
 } bh_options;
 
 /* ---- context ---------------------------------------------------------- */
@@ -350,9 +355,9 @@ bh_status bh_mlp_adam(bh_ctx *ctx, float *params, const float *grad, float *m, f
 
 /* ---- inspection (tests and tools) -------------------------------------- */
 
-/* Sorted Morton keys and the permutation: keys device uint64 [n],
+/* Sorted keys (Morton or Peano-Hilbert, bh_options.curve) and the permutation: keys device uint64 [n],
  * perm device int32 [n] with perm[k] = input row of the k-th particle in
- * Morton order (within each system, systems in order).  Either may be NULL. */
+ * key order (within each system, systems in order).  Either may be NULL. */
 bh_status bh_export_sorted(bh_ctx *ctx, uint64_t *keys, int32_t *perm);
 
 /* Node records, one per slot (stats.n_slots): ints device int32 [slots][6] =

@@ -325,6 +325,7 @@ static bh_status build_common(bh_ctx *c, int32_t nsys, const int64_t *offsets, c
   B.lcursor = B.lcount + 48;
   B.lcells = P<int32_t>(c->lcells);
   B.slot_cap = (int64_t)std::min({c->nodes.bytes / sizeof(NodeRec), c->msum.bytes / 32, c->meta.bytes});
+  B.curve = c->opt.curve;
   const bool quad = c->opt.quadrupole != 0;
   if (quad) {
     const size_t slots = (size_t)B.slot_cap;
@@ -431,6 +432,7 @@ bh_status bh_set_options(bh_ctx *c, const bh_options *opt) {
   if (opt->split_visits < -1 || (opt->split_visits > 0 && opt->split_visits < 64))
     return fail(c, BH_EINVAL, "split_visits must be -1, 0 or >= 64");
   if (opt->quadrupole != 0 && opt->quadrupole != 1) return fail(c, BH_EINVAL, "quadrupole must be 0 or 1");
+  if (opt->curve != 0 && opt->curve != 1) return fail(c, BH_EINVAL, "curve must be 0 (Morton) or 1 (Peano-Hilbert)");
   c->opt = *opt;
   return BH_OK;
 }

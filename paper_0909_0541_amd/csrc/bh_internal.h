@@ -148,7 +148,7 @@ struct bh_ctx {
   int device = 0;
   int num_cu = 0;
   std::string err;
-  bh_options opt{0, 0, 0, 0};
+  bh_options opt{0, 0, 0, 0, 0};
   int walk_bpc = 0, force_bpc = 0, force_bpc_q = 0, probe_bpc = 0, nb_bpc[3] = {0, 0, 0};  // resident blocks per CU of the persistent kernels
 
   // current tree
@@ -286,6 +286,7 @@ struct TreeBuffers {
   double *qmom;           // nullable: FP64 [slots][6] second moments (xx, yy, zz, xy, xz, yz)
   float4 *qpack;          // with qmom: FP32 [slots][2] 3 (xx, yy, zz, xy), (3 xz, 3 yz, T, 1.5 T), T the trace
   int8_t *meta;           // per slot: 32 * kind + level (export only)
+  int curve;              // key order: 0 Morton, 1 Peano-Hilbert
   int32_t *lcount, *loff, *lcursor;  // cells per level: counts, offsets [23], scatter cursors
   int32_t *lcells;                   // cell owner positions grouped by level
   int64_t slot_cap;       // capacity of nodes/msum/meta in slots

@@ -131,8 +131,35 @@ __device__ __forceinline__ uint64_t spread3(uint32_t v) {
   return x;
 }
 
+// Peano-Hilbert order (the transposed-index construction of J. Skilling,
+// 2004): from the top bit down, the lower bits of x are inverted where an
+// axis has the current bit set, and exchanged between x and that axis where
+// it has not; a Gray decode across the axes then gives the "transpose" of
+// the index, whose bits interleaved level by level (x first) are the index.
+// Consecutive indices are face-adjacent cells and every aligned cube is one
+// contiguous index range, so the octal digits still name the octree's cells.
+__device__ __forceinline__ void hilbert_transpose(uint32_t (&x)[3]) {
+  for (int b = kKeyLevels - 1; b >= 1; --b) {
+    const uint32_t bit = 1u << b, low = bit - 1u;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const bool set = (x[a] & bit) != 0u;
+      const uint32_t sw = (x[0] ^ x[a]) & low;  // (0 for the x axis itself)
+      x[0] ^= set ? low : sw;
+      x[a] ^= set ? 0u : sw;
+    }
+  }
+  x[1] ^= x[0];
+  x[2] ^= x[1];
+  uint32_t flip = 0u;
+  for (int b = kKeyLevels - 1; b >= 1; --b)
+    if (x[2] & (1u << b)) flip ^= (1u << b) - 1u;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) x[a] ^= flip;
+}
+
 __global__ void k_keys(const double *__restrict__ pos, const double *__restrict__ mass, int64_t n,
-                       const int32_t *__restrict__ sys_in, const SysInfo *__restrict__ sys,
+                       const int32_t *__restrict__ sys_in, const SysInfo *__restrict__ sys, int curve,
                        uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, DevInfo *info) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -140,6 +167,7 @@ __global__ void k_keys(const double *__restrict__ pos, const double *__restrict_
   uint32_t q[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) q[k] = quantise(pos[3 * i + k], S.lo[k], S.scale);
+  if (curve) hilbert_transpose(q);
   // x bit is the most significant of each octal digit
   keys[i] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
   vals[i] = (uint32_t)i;
@@ -446,7 +474,7 @@ __global__ void k_moments(int lev, const int32_t *__restrict__ lcells, const int
                           const int32_t *__restrict__ cslot,
                           const int32_t *__restrict__ cfc, const int32_t *__restrict__ nchild,
                           const int32_t *__restrict__ cfirst, const int32_t *__restrict__ ccount,
-                          const uint64_t *__restrict__ keys, const SysInfo *__restrict__ sys, int nsys, int64_t n,
+                          const double *__restrict__ spos, const SysInfo *__restrict__ sys, int nsys, int64_t n,
                           int64_t cap, NodeRec *__restrict__ nodes, double *__restrict__ msum,
                           double *__restrict__ qmom, float4 *__restrict__ qpack,
                           int8_t *__restrict__ meta, DevInfo *info) {
@@ -486,8 +514,10 @@ __global__ void k_moments(int lev, const int32_t *__restrict__ lcells, const int
     else always_open = true;
   }
   const double l = ldexp(S.side, -geo);
+  // the cell's coordinates from its first member's (for either curve)
   uint32_t q[3];
-  key_cells(keys[cfirst[j]], q);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) q[k] = quantise(spos[3 * (int64_t)cfirst[j] + k], S.lo[k], S.scale);
   double c[3], com[3];
   const double mv[3] = {mx, my, mz};
   for (int k = 0; k < 3; ++k) {
@@ -564,7 +594,7 @@ void build_tree_device(TreeBuffers &B, hipStream_t s) {
     return;
   }
   if (nsys > 1) k_system_of_input<<<blocks_for(n), 256, 0, s>>>(B.sys, nsys, n, B.sys_in);
-  k_keys<<<blocks_for(n), 256, 0, s>>>(B.pos, B.mass, n, nsys > 1 ? B.sys_in : nullptr, B.sys, B.keys[0],
+  k_keys<<<blocks_for(n), 256, 0, s>>>(B.pos, B.mass, n, nsys > 1 ? B.sys_in : nullptr, B.sys, B.curve, B.keys[0],
                                         B.vals[0], B.info);
   int cur = radix_sort_pairs(B.keys[0], B.keys[1], B.vals[0], B.vals[1], n, 0, 64, B.hist, B.scan_tmp, s);
   if (nsys > 1) {
@@ -595,7 +625,7 @@ void build_tree_device(TreeBuffers &B, hipStream_t s) {
   for (int lev = kKeyLevels; lev >= 0; --lev)
     k_moments<<<mgrid, 256, 0, s>>>(lev, B.lcells, B.loff, B.level, B.cparent,
                                                                         B.cslot, B.cfc, B.nchild, B.cfirst, B.ccount,
-                                                                        keys, B.sys, nsys, n, B.slot_cap, B.nodes,
+                                                                        B.spos, B.sys, nsys, n, B.slot_cap, B.nodes,
                                                                         B.msum, B.qmom, B.qpack, B.meta, B.info);
 }
 
