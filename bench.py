@@ -13,10 +13,11 @@ Prints one JSON line.  value = tree-force interactions per second of whole
 steps at that theta (sum over members of list length - 1, divided by the
 step time).  Beside it: particles/s; the learned per-group theta at the same
 error (its output shift bisected the same way, features + network in the
-step); the quadrupole option at the same error; the neighbour search with SPH
-densities at 64 neighbours per particle; the per-particle walk at the
-same error; the workload's own theta of 0.6; the roofline of the dominant kernel
-(the force sum, FP32 VALU); and the FP64 CPU oracle's throughput.
+step); the quadrupole option and Peano-Hilbert order at the same error; the
+neighbour search with SPH densities at 64 neighbours per particle; the
+per-particle walk at the same error; the workload's own theta of 0.6; the
+roofline of the dominant kernel (the force sum, FP32 VALU); and the FP64 CPU
+oracle's throughput.
 """
 from __future__ import annotations
 
@@ -85,6 +86,7 @@ def parse():
     ap.add_argument("--no-particle", action="store_true", help="skip the per-particle walk A/B leg")
     ap.add_argument("--no-quadrupole", action="store_true", help="skip the quadrupole A/B leg")
     ap.add_argument("--no-neighbors", action="store_true", help="skip the neighbour-search leg")
+    ap.add_argument("--no-hilbert", action="store_true", help="skip the Peano-Hilbert order A/B leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-systems leg")
     ap.add_argument("--copy-check-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the timed steps, "
@@ -213,47 +215,46 @@ def particle_leg(args, ctx, judge, dpos, dmass, w, line):
             "step": "tree build + per-particle walk and sum (the paper's threaded-tree kernel form)"}
 
 
-def quadrupole_leg(args, judge, dpos, dmass, w, line, inter_mono):
-    """The quadrupole option as an A/B at the same RMS force error: the same
-    step with every cell entry carrying its second-order term, theta bisected
-    to the target error (a larger theta, shorter lists, dearer cell terms),
-    timed as a graph replay checked bit for bit against its eager step."""
+def variant_leg(args, judge, dpos, dmass, w, line, inter_ref, step, **opts):
+    """An option of the same step as an A/B at the same RMS force error:
+    theta bisected to the target error with the option set, timed as a graph
+    replay checked bit for bit against its eager step."""
     import numpy as np
     import torch
 
     from paper_0909_0541_amd import autotune, bh, learned
 
     n = dpos.shape[0]
-    qctx = bh.Context(timing=True, waves_per_cu=args.waves_per_cu, quadrupole=True)
-    q = learned.Stepper(qctx, dpos, dmass, w.eps, w.n_crit)
+    vctx = bh.Context(timing=True, waves_per_cu=args.waves_per_cu, **opts)
+    v = learned.Stepper(vctx, dpos, dmass, w.eps, w.n_crit)
 
     def rms_of(th):
-        q(theta=th)
-        return judge.rms(q.acc)
+        v(theta=th)
+        return judge.rms(v.acc)
 
     theta, r = learned.bisect(rms_of, args.theta_lo, 1.0, args.target_rms)
-    ms_eager, st = learned.timed_steps(q, args.steps, args.warmup, theta=theta)
+    ms_eager, st = learned.timed_steps(v, args.steps, args.warmup, theta=theta)
     per = lambda t, k: t / max(k, 1)
     stage = {"build": per(st.t_build_ms, st.n_build_calls), "groups": per(st.t_groups_ms, st.n_groups_calls),
              "walk": per(st.t_walk_ms, st.n_walk_calls), "force": per(st.t_force_ms, st.n_force_calls)}
     ms, mode = ms_eager, "eager"
     try:
-        g = bh.Context(waves_per_cu=args.waves_per_cu, quadrupole=True)
+        g = bh.Context(waves_per_cu=args.waves_per_cu, **opts)
         g.graph_capture(np.array([0, n], dtype=np.int64), dpos, dmass, w.n_crit, [w.eps], [theta])
         ms_g = autotune.time_graph(g, args.steps, args.warmup)
         gst = g.get_stats()
-        if not gst.error_flags and gst.interactions == st.interactions and torch.equal(g._graph_io[2], q.acc):
+        if not gst.error_flags and gst.interactions == st.interactions and torch.equal(g._graph_io[2], v.acc):
             ms, mode = ms_g, "graph"
         del g
     except (RuntimeError, bh.BHError):
         pass
-    return {"theta": theta, "rms_force_error": judge.rms(q.acc), "ms_per_step": ms, "step_mode": mode,
-            "eager_ms_per_step": ms_eager, "interactions_per_step": st.interactions,
+    return {"options": opts, "theta": theta, "rms_force_error": judge.rms(v.acc), "ms_per_step": ms,
+            "step_mode": mode, "eager_ms_per_step": ms_eager, "interactions_per_step": st.interactions,
             "interactions_per_s": st.interactions / (ms * 1e-3), "particles_per_s": n / (ms * 1e-3),
-            "stage_ms": stage, "max_list": st.max_list,
-            "interactions_vs_monopole": st.interactions / inter_mono,
-            "particles_per_s_vs_monopole": (n / (ms * 1e-3)) / line["particles_per_s"],
-            "step": "tree build with second moments, groups, list walk, force sum with quadrupole terms"}
+            "stage_ms": stage, "max_list": st.max_list, "groups": st.n_groups,
+            "interactions_vs_default": st.interactions / inter_ref,
+            "particles_per_s_vs_default": (n / (ms * 1e-3)) / line["particles_per_s"],
+            "step": step}
 
 
 FP64_VALU_PEAK_TFLOPS = 78.6    # MI355X published FP64 vector peak
@@ -444,7 +445,13 @@ def main():
             "interactions_per_step": st2.interactions, "stage_ms": s2,
             "force_kernel_tflops": FLOPS_PER_INTERACTION * st2.interactions / (s2["force"] * 1e-3) / 1e12}
     if calib is not None and not args.no_quadrupole:
-        line["quadrupole"] = quadrupole_leg(args, judge, dpos, dmass, w, line, inter)
+        line["quadrupole"] = variant_leg(
+            args, judge, dpos, dmass, w, line, inter,
+            "tree build with second moments, groups, list walk, force sum with quadrupole terms", quadrupole=True)
+    if calib is not None and not args.no_hilbert:
+        line["hilbert"] = variant_leg(
+            args, judge, dpos, dmass, w, line, inter,
+            "the same step with Peano-Hilbert keys (particles, children and groups in curve order)", curve=1)
     if not args.no_neighbors:
         line["neighbors"] = neighbor_leg(args, dpos, dmass, w)
     if calib is not None and not args.no_particle:
