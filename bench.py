@@ -44,10 +44,10 @@ FLOPS_PER_INTERACTION = 20      # 3 sub, 3 FMA (r^2), rsqrt, 3 mul, 3 FMA (acc),
 # device copy of known size), valid only for the kernel source it was taken on.
 TRAFFIC = {
     # clustered box, 2,097,152 particles, theta 0.4203125 (the 1e-3 RMS theta):
-    # FETCH_SIZE 2852897.1 KiB x 1.99987 (a 512 MiB device copy reads as
-    # 262160.75 KiB) + WRITE_SIZE 155006.9 KiB x 1.0 (the copy writes 524288 KiB)
-    "clustered_2m": {"theta": 0.4203125, "bytes_per_launch": 6001086952,
-                     "k_force_sha256": "2be925f64e4395089096f444cb0d9b5934bb8f5f1bf0917d7e37cd740c71e977"},
+    # FETCH_SIZE 2830548.1 KiB x 1.99987 (a 512 MiB device copy reads as
+    # 262160.69 KiB) + WRITE_SIZE 145878.8 KiB x 1.0 (the copy writes 524288 KiB)
+    "clustered_2m": {"theta": 0.4203125, "bytes_per_launch": 5945973442,
+                     "k_force_sha256": "62fa39ed51d4b632e2aa53196c44a7abed544f7f661602e52b7600e59dfb1141"},
 }
 
 
