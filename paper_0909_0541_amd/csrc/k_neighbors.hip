@@ -10,8 +10,8 @@
 // whose particles all lie farther than the group's largest radius from the
 // group's bounding box: every particle of a cell lies within
 // (sqrt(3)/2) l + s of its centre of mass (l the cube side, s the distance of
-// the centre of mass from the cube's centre).  A particle leaf inside the
-// box grown by that radius is a candidate; candidates collect in LDS and are
+// the centre of mass from the cube's centre).  A particle leaf within that
+// radius of the box is a candidate; candidates collect in LDS and are
 // tested against every member, one member per lane, in FP64 with the
 // squared distance (dx^2 + dy^2) + dz^2 rounded as written, so the decision
 // r^2 < h_i^2 is the same as a plain CPU evaluation.  A candidate's index,
@@ -160,17 +160,20 @@ __global__ __launch_bounds__(kWave) void k_neighbors(NeighborArgs a) {
     }
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) hmax = fmax(hmax, shfl_xor_d(hmax, d));
-    // the group's box grown by the largest radius, with a margin above the
-    // rounding of these sums
+    // the group's box, widened by a margin above the rounding of the
+    // distance sums, and the largest radius with a relative margin: a
+    // neighbour of any member lies within rad of the box (a rounded box,
+    // not the box grown into a cube)
     double elo[3], ehi[3], cpad = 0.0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const double lo = a.gbox[6 * (int64_t)g + k], hi = a.gbox[6 * (int64_t)g + 3 + k];
-      const double pad = hmax * (1.0 + 1e-9) + 1e-15 * fmax(fabs(lo), fabs(hi));
+      const double pad = 1e-15 * fmax(fabs(lo), fabs(hi)) + 1e-300;
       elo[k] = lo - pad;
       ehi[k] = hi + pad;
-      cpad += 1e-15 * fmax(fabs(lo), fabs(hi));
+      cpad += pad;
     }
+    const double rad = hmax * (1.0 + 1e-9) + cpad;
 
     int sp = 1, ncand = 0;
     if (lane == 0) stk[0] = make_int2(gs, 1);
@@ -224,7 +227,7 @@ __global__ __launch_bounds__(kWave) void k_neighbors(NeighborArgs a) {
           d2 += ek * ek;
         }
         if (r.child < 0) {
-          is_cand = r.count > 0 && d2 == 0.0;  // a particle inside the grown box
+          is_cand = r.count > 0 && d2 <= rad * rad;  // a particle within rad of the box
           j = r.first;
           px = r.com[0];
           py = r.com[1];
@@ -232,7 +235,7 @@ __global__ __launch_bounds__(kWave) void k_neighbors(NeighborArgs a) {
           pm = r.m;
         } else {
           // every particle of the cell lies within R of its centre of mass
-          const double R = (kHalfSqrt3 * r.l + r.s) * (1.0 + 1e-9) + cpad;
+          const double R = (kHalfSqrt3 * r.l + r.s) * (1.0 + 1e-9) + rad;
           push = !(d2 > R * R);
           rng = make_int2(r.child, r.nchild);
         }
