@@ -89,3 +89,28 @@ def test_hilbert_batch_equals_standalone(gpu):
         s.make_groups(64)
         sa, sp = s.compute_forces(float(eps[k]), float(theta[k]))
         assert torch.equal(sa, a[lo:hi]) and torch.equal(sp, p[lo:hi]), f"system {k}"
+
+
+def test_hilbert_with_quadrupoles_and_neighbors(gpu):
+    """The options compose: quadrupole sums in Peano-Hilbert order match the
+    oracle's in that order, and the neighbour search gives the same counts
+    and densities in either order."""
+    pos, mass = inputs.clustered(15000, 12, n_halos=30)[:2]
+    eps, theta, n_crit = 1e-3, 0.6, 64
+    c = gpu.Context(curve=1, quadrupole=True)
+    c.build_tree(to_dev(pos), to_dev(mass))
+    G = c.make_groups(n_crit)
+    acc, pot = c.compute_forces(eps, theta)
+    assert c.get_stats().error_flags == 0
+    t = oracle.Tree(pos, mass, curve=1)
+    assert t.groups(n_crit) == G
+    ref = t.forces(eps, theta, quadrupole=True)
+    check_forces(acc.cpu().numpy().astype(np.float64), pot.cpu().numpy().astype(np.float64), ref)
+    h = to_dev(np.full(pos.shape[0], 0.02))
+    ch, rh = c.neighbors(h, count=True, rho=True)
+    m = gpu.Context()
+    m.build_tree(to_dev(pos), to_dev(mass))
+    m.make_groups(n_crit)
+    cm, rm = m.neighbors(h, count=True, rho=True)
+    assert torch.equal(ch, cm)
+    np.testing.assert_allclose(rh.cpu().numpy(), rm.cpu().numpy(), rtol=1e-12)
