@@ -17,7 +17,7 @@ from paper_0909_0541_amd import inputs
 pytestmark = pytest.mark.gpu
 
 # workload -> theta at 1e-3 RMS (the benchmark's bisection on its judge sample)
-CASES = {"clustered_2m": 0.4203125, "clustered_4m": 0.3328125, "clustered_8m": 0.3546875}
+CASES = {"clustered_2m": 0.4203125, "clustered_4m": 0.3328125, "clustered_8m": 0.34921875}
 
 
 @pytest.mark.parametrize("name", list(CASES))
