@@ -542,16 +542,19 @@ __global__ void k_moments(int lev, const int32_t *__restrict__ lcells, const int
   nodes[slot] = r;
   if (qmom) {
     // second moments about the centre of mass from the children's own, each
-    // shifted to this centre (parallel axes); a particle's own are zero
+    // shifted to this centre (parallel axes); a particle's own are zero.  A
+    // child's mass and centre of mass come from its raw sums (its kind from
+    // meta), not from its 64-byte record; a massless child adds nothing.
     double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int ci = 0; ci < nc; ++ci) {
       const int cs = c0 + ci;
-      const NodeRec &q = nodes[cs];
-      const double mc = q.m;
-      const double ex = __dsub_rn(q.com[0], com[0]), ey = __dsub_rn(q.com[1], com[1]),
-                   ez = __dsub_rn(q.com[2], com[2]);
+      const double *q = msum + 4 * (int64_t)cs;
+      const double mc = q[0];
+      if (!(mc > 0.0)) continue;
+      const double ex = __dsub_rn(q[1] / mc, com[0]), ey = __dsub_rn(q[2] / mc, com[1]),
+                   ez = __dsub_rn(q[3] / mc, com[2]);
       const double sh[6] = {mc * ex * ex, mc * ey * ey, mc * ez * ez, mc * ex * ey, mc * ex * ez, mc * ey * ez};
-      const bool leaf = q.child < 0;
+      const bool leaf = (meta[cs] >> 5) == kParticle;
 #pragma unroll
       for (int k = 0; k < 6; ++k) S[k] = __dadd_rn(S[k], leaf ? sh[k] : __dadd_rn(qmom[6 * (int64_t)cs + k], sh[k]));
     }
