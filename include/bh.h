@@ -376,7 +376,7 @@ bh_status bh_export_nodes(bh_ctx *ctx, int32_t *ints, double *reals);
  * form), the squared distance (dx^2 + dy^2) + dz^2 evaluated in FP64 as
  * written.  h: device FP64 [n], input order, positive and finite (else
  * BH_EINVAL at the next synchronising call).  Outputs, device, input order,
- * each nullable (at least one): count int32 [n], the neighbour counts; rho
+ * each nullable (at least one when n > 0): count int32 [n], the neighbour counts; rho
  * FP64 [n], the SPH density m_i W(0, h_i) + sum over neighbours m_j W(r_ij,
  * h_i) with the cubic spline kernel of compact support h (W = 8/(pi h^3)
  * (1 - 6q^2 + 6q^3) for q = r/h < 1/2, 16/(pi h^3) (1 - q)^3 for q < 1);

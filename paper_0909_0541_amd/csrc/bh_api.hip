@@ -1136,10 +1136,13 @@ bh_status bh_neighbors(bh_ctx *c, const double *h, int32_t *count, double *rho, 
   if (!c->have_tree) return fail(c, BH_ESTATE, "neighbour search requested before a tree was built");
   if (!c->have_groups) return fail(c, BH_ESTATE, "neighbour search requested before bh_make_groups");
   if (c->n > 0 && !h) return fail(c, BH_EINVAL, "h must not be NULL");
+  if (c->n == 0) {  // nothing to search (empty outputs may come as NULL)
+    c->have_neighbors = true;
+    return BH_OK;
+  }
   if ((offsets == nullptr) != (nbr == nullptr)) return fail(c, BH_EINVAL, "offsets and nbr go together");
   if (!count && !rho && !nbr) return fail(c, BH_EINVAL, "no output requested");
   c->have_neighbors = true;
-  if (c->n == 0) return BH_OK;
   const int variant = c->n_crit <= 64 ? 0 : (c->n_crit <= 128 ? 1 : 2);
   if (!c->nb_bpc[variant]) c->nb_bpc[variant] = neighbors_blocks_per_cu(c->n_crit);
   const int grid = c->num_cu * (c->opt.waves_per_cu > 0 ? c->opt.waves_per_cu : c->nb_bpc[variant]);

@@ -114,3 +114,28 @@ def test_hilbert_with_quadrupoles_and_neighbors(gpu):
     cm, rm = m.neighbors(h, count=True, rho=True)
     assert torch.equal(ch, cm)
     np.testing.assert_allclose(rh.cpu().numpy(), rm.cpu().numpy(), rtol=1e-12)
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 65])
+def test_options_small_and_empty_inputs(gpu, n):
+    """Edge sizes with every option: Peano-Hilbert order with quadrupole sums
+    against the oracle, and the neighbour search against brute force."""
+    pos = np.random.default_rng(n + 3).normal(size=(n, 3))
+    mass = np.full(n, 1.0)
+    c = gpu.Context(curve=1, quadrupole=True)
+    c.build_tree(to_dev(pos.reshape(n, 3)), to_dev(mass))
+    G = c.make_groups(8)
+    acc, pot = c.compute_forces(0.05, 0.6)
+    h = np.full(n, 1.0)
+    cnt, rho = c.neighbors(to_dev(h), count=True, rho=True)
+    assert c.get_stats().error_flags == 0
+    if n == 0:
+        assert G == 0
+        return
+    t = oracle.Tree(pos, mass, curve=1)
+    assert t.groups(8) == G
+    ref = t.forces(0.05, 0.6, quadrupole=True)
+    check_forces(acc.cpu().numpy().astype(np.float64), pot.cpu().numpy().astype(np.float64), ref)
+    nref = oracle.neighbors(pos, mass, h)
+    assert np.array_equal(cnt.cpu().numpy().astype(np.int64), nref["count"])
+    np.testing.assert_allclose(rho.cpu().numpy(), nref["rho"], rtol=1e-12)
