@@ -59,8 +59,9 @@ typedef enum {
 
 /* Largest group size accepted by bh_make_groups. */
 #define BH_MAX_NCRIT 256
-/* Largest particle count of one tree (all systems together). */
-#define BH_MAX_N (1LL << 30)
+/* Largest particle count of one tree (all systems together): node slots
+ * (at most 2 n + systems) and particle indices are int32 on the device. */
+#define BH_MAX_N ((1LL << 30) - (1LL << 17))
 
 typedef struct {
   int64_t n;             /* particles in the current tree (all systems) */
