@@ -74,3 +74,28 @@ def test_launch_without_capture(gpu):
     c = bh.Context()
     with pytest.raises(bh.BHError):
         c.graph_launch()
+
+
+@pytest.mark.parametrize("opts", [{"quadrupole": True}, {"curve": 1}, {"quadrupole": True, "curve": 1}],
+                         ids=["quadrupole", "peano_hilbert", "both"])
+def test_replays_equal_eager_with_options(gpu, opts):
+    bh = gpu
+    pos, mass = inputs.clustered(30000, 43, n_halos=30)[:2]
+    off = np.array([0, pos.shape[0]])
+    dpos, dmass = to_dev(pos), to_dev(mass)
+    e = bh.Context(**opts)
+    e.build_tree(dpos, dmass)
+    e.make_groups(64)
+    a0, p0 = e.compute_forces(1e-3, 0.7)
+    a0, p0 = a0.clone(), p0.clone()
+    c = bh.Context(**opts)
+    acc, pot = c.graph_capture(off, dpos, dmass, 64, np.array([1e-3]), np.array([0.7]))
+    torch.cuda.synchronize()
+    assert torch.equal(acc, a0) and torch.equal(pot, p0), "eager step of the capture"
+    for k in range(3):
+        acc.fill_(float("nan"))
+        torch.cuda.synchronize()
+        c.graph_launch()
+        c.sync()
+        assert torch.equal(acc, a0) and torch.equal(pot, p0), f"replay {k}"
+    assert c.get_stats().error_flags == 0
