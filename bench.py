@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--no-quadrupole", action="store_true", help="skip the quadrupole A/B leg")
     ap.add_argument("--no-neighbors", action="store_true", help="skip the neighbour-search leg")
     ap.add_argument("--no-hilbert", action="store_true", help="skip the Peano-Hilbert order A/B leg")
+    ap.add_argument("--curve", type=int, default=0, choices=(0, 1),
+                    help="key order of the headline step: 0 Morton (default), 1 Peano-Hilbert (for counter runs)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-systems leg")
     ap.add_argument("--copy-check-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the timed steps, "
@@ -326,7 +328,7 @@ def main():
     n = pos.shape[0]
     dpos = torch.as_tensor(pos, device="cuda")
     dmass = torch.as_tensor(mass, device="cuda")
-    ctx = bh.Context(timing=True, waves_per_cu=args.waves_per_cu)
+    ctx = bh.Context(timing=True, waves_per_cu=args.waves_per_cu, curve=args.curve)
     judge = learned.Judge(ctx, dpos, dmass, w.eps, args.judge_sample)
     fixed = learned.Stepper(ctx, dpos, dmass, w.eps, w.n_crit)
 
@@ -366,7 +368,7 @@ def main():
     from paper_0909_0541_amd import autotune
     step_mode, graph_error = "graph", None
     try:
-        gctx = bh.Context(waves_per_cu=args.waves_per_cu)
+        gctx = bh.Context(waves_per_cu=args.waves_per_cu, curve=args.curve)
         gctx.graph_capture(np.array([0, n], dtype=np.int64), dpos, dmass, w.n_crit, [w.eps], [theta])
         ms_per_step = autotune.time_graph(gctx, args.steps, args.warmup)
         gst = gctx.get_stats()
@@ -394,7 +396,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "description": w.description, "n": n, "eps": w.eps, "theta": theta,
                    "workload_theta": w.theta, "n_crit": w.n_crit,
-                   "theta_mode": "fixed" if calib is None else "fixed, bisected to the target RMS force error"},
+                   "theta_mode": "fixed" if calib is None else "fixed, bisected to the target RMS force error",
+                   "key_order": "Peano-Hilbert" if args.curve else "Morton"},
         "particles_per_s": n / (ms_per_step * 1e-3),
         "step": ("one HIP graph replay: tree build, groups, list walk, force sum" if step_mode == "graph"
                  else f"eager calls (graph replay not used: {graph_error})"),
