@@ -1,7 +1,9 @@
 // Device-wide exclusive scan of int32 values and a fill kernel.
 //
 // Three launches: per-tile sums, one-block scan of the tile sums, per-tile
-// rescan plus tile offset.  A tile is 256 threads x 16 items.
+// rescan plus tile offset.  A tile is 256 threads x 16 items.  Up to
+// kScanDirectTiles tiles the middle launch is left out: each tile adds up
+// the sums of the tiles before it itself (at most 4 KiB of reads per tile).
 #include "bh_device.h"
 
 namespace bh {
@@ -11,6 +13,7 @@ namespace {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;
+constexpr int64_t kScanDirectTiles = 1024;
 
 __device__ __forceinline__ int block_exclusive_sum(int v, int *lds_wave, int *total) {
   const int lane = lane_id();
@@ -63,9 +66,21 @@ __global__ __launch_bounds__(1024) void k_scan_sums(int32_t *__restrict__ sums, 
   if (threadIdx.x == 0 && total) *total = tot;
 }
 
+// Direct: sums[] holds each tile's own sum; the tile's offset is the sum of
+// those before it, and the last tile writes the total.  Otherwise sums[]
+// holds the offsets already.
+template <bool Direct>
 __global__ __launch_bounds__(kScanThreads) void k_tile_scan(const int32_t *in, int32_t *out, int64_t n,
-                                                            const int32_t *__restrict__ sums) {
+                                                            const int32_t *__restrict__ sums, int32_t *total) {
   __shared__ int lds[kScanThreads / kWave];
+  int tile_off;
+  if (Direct) {
+    int p = 0;
+    for (int k = threadIdx.x; k < (int)blockIdx.x; k += kScanThreads) p += sums[k];
+    block_exclusive_sum(p, lds, &tile_off);
+  } else {
+    tile_off = sums[blockIdx.x];
+  }
   // blocked layout: thread t owns items [t*16, t*16+16) of the tile
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   int v[kScanItems];
@@ -77,13 +92,14 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(const int32_t *in, i
     s += v[k];
   }
   int tot;
-  int off = block_exclusive_sum(s, lds, &tot) + sums[blockIdx.x];
+  int off = block_exclusive_sum(s, lds, &tot) + tile_off;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     int64_t i = base + k;
     if (i < n) out[i] = off;
     off += v[k];
   }
+  if (Direct && total && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *total = tile_off + tot;
 }
 
 __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
@@ -107,8 +123,12 @@ void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *tot
   }
   int32_t *sums = (int32_t *)tmp;
   k_tile_sums<<<(unsigned)nt, kScanThreads, 0, s>>>(in, n, sums);
+  if (nt <= kScanDirectTiles) {
+    k_tile_scan<true><<<(unsigned)nt, kScanThreads, 0, s>>>(in, out, n, sums, total);
+    return;
+  }
   k_scan_sums<<<1, 1024, 0, s>>>(sums, nt, total);
-  k_tile_scan<<<(unsigned)nt, kScanThreads, 0, s>>>(in, out, n, sums);
+  k_tile_scan<false><<<(unsigned)nt, kScanThreads, 0, s>>>(in, out, n, sums, nullptr);
 }
 
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
