@@ -212,7 +212,7 @@ bh_status bh_compute_forces(bh_ctx *ctx, double eps, double theta, const float *
 bh_status bh_compute_forces_batch(bh_ctx *ctx, const double *eps_sys, const double *theta_sys,
                                   const float *theta_group, float *acc, float *pot);
 
-/* The paper's own GPU form (Sec. 3.1, Fig. "treegpu"): every particle walks
+/* The paper's own GPU form (Sec. 3.4, Fig. "treegpu"): every particle walks
  * the tree by itself over a threaded tree ("next" skips a subtree, "more" is
  * the first child) and sums Eq. (1) on the way, with no shared list.  The
  * opening test is the group test of bh_compute_forces with one-particle
@@ -296,7 +296,7 @@ bh_status bh_energy(bh_ctx *ctx, int64_t n, const double *vel, const double *mas
 /* ---- learned per-group theta ------------------------------------------- */
 
 /* The paper fixes one opening angle and studies its accuracy/work trade-off
- * (Sec. 4).  These calls let a small network choose theta per group instead:
+ * (Sec. 3.5, Table "theta").  These calls let a small network choose theta per group instead:
  * 12 group features -> tanh(64) -> tanh(64) -> theta = 0.3 + 0.7 sigmoid(y +
  * shift).  Features (FP32, per group, from the current tree and groups; c the
  * member count, c_g the box centre, R the box half-diagonal, x_g and m_g the
@@ -370,7 +370,7 @@ bh_status bh_export_nodes(bh_ctx *ctx, int32_t *ints, double *reals);
 
 /* ---- neighbour search (SPH) ------------------------------------------- */
 
-/* The general treewalk of Sec. 3.2 (Fig. "general_treewalk") applied to a
+/* The general treewalk of Sec. 3.3 (Fig. "general_treewalk") applied to a
  * short-range interaction, on the current tree and groups (bh_make_groups
  * first).  The neighbours of particle i are the particles j != i of the same
  * tree with |x_j - x_i| < h_i (each particle's own radius: the "gather"

@@ -735,7 +735,7 @@ void oracle_tree_group_info(void *h, int64_t *first, int64_t *count, double *lo,
   }
 }
 
-/* ---- neighbour search (the general treewalk of Sec. 3.2 applied to short-
+/* ---- neighbour search (the general treewalk of Sec. 3.3 applied to short-
  * range interactions, as in SPH) ------------------------------------------
  *
  * The plain definition, by brute force over all pairs: the neighbours of

@@ -1,7 +1,7 @@
 """FP64 reference of the per-group opening-angle network (test infrastructure only).
 
 The paper fixes one opening angle for all particles and shows that it trades
-accuracy for work (Sec. 4, the run-time and error study over theta).  The
+accuracy for work (Sec. 3.5, the run-time and error study over theta in Table "theta").  The
 learned part chooses theta per group instead: a multilayer perceptron maps 12
 features of a group (`features`) to theta in [0.3, 1.0].  This module is the
 plain FP64 definition the GPU kernels are checked against:

@@ -1,7 +1,7 @@
 // Per-group opening angle chosen by a small network (12 -> 64 -> 64 -> 1).
 //
 // The paper uses one theta for every particle and studies how it trades
-// accuracy for work (Sec. 4).  Here each group gets its own theta from 12
+// accuracy for work (Sec. 3.5, Table "theta").  Here each group gets its own theta from 12
 // features that describe how it sits in the surrounding mass (c members,
 // c_g box centre, R box half-diagonal, x_g and m_g the members' centre of mass
 // and mass, A1 the smallest cell with at least two sub-cells (not a bucket)

@@ -1,4 +1,4 @@
-// Neighbour search and SPH density: the general treewalk of Sec. 3.2 (Fig.
+// Neighbour search and SPH density: the general treewalk of Sec. 3.3 (Fig.
 // "general_treewalk") applied to a short-range interaction, as in smoothed
 // particle hydrodynamics, the application the paper names.
 //

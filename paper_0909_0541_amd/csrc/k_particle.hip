@@ -1,5 +1,5 @@
 // Per-particle tree walk: the paper's own GPU form (Fig. "treegpu", the
-// threaded tree of Sec. 3.1), where each particle walks the tree by itself
+// threaded tree of Sec. 3.4), where each particle walks the tree by itself
 // and sums its forces on the way, with no shared list.
 //
 // Threading: every node gets a "next" pointer, the node that follows its

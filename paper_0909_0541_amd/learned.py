@@ -1,7 +1,7 @@
 """Learned per-group opening angle: labels, training and calibration.
 
 The paper fixes one theta for all particles and measures how run time and
-accuracy move with it (Sec. 4, the theta study).  With groups the error a
+accuracy move with it (Sec. 3.5, Table "theta").  With groups the error a
 given theta makes differs a lot from group to group: where the pull of the
 surrounding mass nearly cancels, the relative force error is large and a
 small theta is needed; elsewhere a large theta is accurate enough.  This

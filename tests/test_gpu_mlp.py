@@ -59,8 +59,49 @@ def test_features_match_oracle(gpu, case):
     assert np.all(err <= 1e-6 * np.maximum(1.0, np.abs(f_orc))), (name, err.max())
 
 
+def _bf16_bound(p, x, mu, sigma, lam=6.0):
+    """Bound on |theta_bf16 - theta_fp64| per row, derived from the layer
+    widths and the bfloat16 unit roundoff u_b = 2^-8 (8 significant bits).
+
+    Layer 1 rounds both operands of each of its 12 products (x' and W1) to
+    bfloat16, layer 2 both operands of its 64 products (h1 and W2); the
+    products are accumulated in FP32 (unit roundoff 2^-24, at most n
+    roundings for n terms).  Round-to-nearest errors are bounded by
+    u_b |v| and, in the probabilistic model of rounding errors (Higham and
+    Mary, SIAM J. Sci. Comput. 41, 2019), independent with mean zero, so by
+    Hoeffding's inequality a sum of such errors exceeds lam times the root of
+    the sum of their squared bounds with probability at most
+    2 exp(-lam^2 / 2) (3e-8 for lam = 6).  The error is carried through tanh
+    (Lipschitz 1; FP32 tanh within 4 ulps), the output layer (FP32) and the
+    sigmoid (Lipschitz 1/4), scaled by the theta span 0.7."""
+    w = mlp.unpack(np.asarray(p, dtype=np.float64))
+    ub, u = 2.0 ** -8, 2.0 ** -24
+    xn = (np.asarray(x, np.float64) - mu) / sigma
+    W1, W2, w3 = w["W1"], w["W2"], w["w3"]
+    e1 = ub * np.sqrt(2.0 * ((xn[:, None, :] * W1[None, :, :]) ** 2).sum(-1)) \
+        + 13 * u * (np.abs(xn) @ np.abs(W1).T + np.abs(w["b1"]))
+    h1 = np.tanh(xn @ W1.T + w["b1"])
+    d1 = np.sqrt(e1 ** 2 + (ub * np.abs(h1)) ** 2) + 4 * u
+    e2 = np.sqrt((d1 ** 2) @ (W2 ** 2).T + ub ** 2 * ((h1 ** 2) @ (W2 ** 2).T)) \
+        + 65 * u * (np.abs(h1) @ np.abs(W2).T + np.abs(w["b2"]))
+    h2 = np.tanh(h1 @ W2.T + w["b2"])
+    d2 = e2 + 4 * u
+    ey = np.sqrt((d2 ** 2) @ (w3 ** 2)) + 65 * u * (np.abs(h2) @ np.abs(w3) + abs(w["b3"][0]))
+    return mlp.THETA_SPAN * (0.25 * lam * ey + 4 * u)
+
+
+def _check_inference(th, p, x, mu, sigma, shift):
+    """Acceptance: the plain FP64 network within the derived bfloat16 bound,
+    and never more than 1e-2 in theta."""
+    full, _ = mlp.forward(p, x, mu.astype(np.float64), sigma.astype(np.float64), shift)
+    tol = np.minimum(_bf16_bound(p, x, mu.astype(np.float64), sigma.astype(np.float64)), 1e-2)
+    err = np.abs(th - full)
+    assert np.all(err <= tol), (err.max(), float(tol[np.argmax(err - tol)]))
+    return err
+
+
 @pytest.mark.parametrize("rows", [0, 1, 17, 1003, 4096])
-def test_inference_matches_bf16_oracle(gpu, rows):
+def test_inference_matches_fp64_network(gpu, rows):
     bh = gpu
     p, mu, sigma = _net(3)
     x = np.random.default_rng(rows).normal(size=(rows, 12)).astype(np.float32) * 3.0
@@ -69,18 +110,29 @@ def test_inference_matches_bf16_oracle(gpu, rows):
     th = th.cpu().numpy().astype(np.float64)
     if rows == 0:
         return
-    ref = mlp.forward_bf16(p, x, mu, sigma, 0.25)
-    # Same bfloat16 operands on both sides; the sums differ in FP32 rounding
-    # order (relative ~1e-6), which can flip the bfloat16 rounding of a first-
-    # layer activation (a step of 2^-8 relative) now and then.  One flip moves
-    # theta by at most 0.7/4 * |w3|max * |W2|max * 2^-8.
-    one_flip = 0.7 / 4 * np.abs(mlp.unpack(p)["w3"]).max() * np.abs(mlp.unpack(p)["W2"]).max() * 2.0 ** -8
-    err = np.abs(th - ref)
-    assert np.quantile(err, 0.99) <= 1e-5, np.quantile(err, 0.99)
-    assert err.max() <= 4 * one_flip + 1e-5, (err.max(), one_flip)
-    # and it is the network of the FP64 definition up to bfloat16 precision
-    full, _ = mlp.forward(p, x, mu, sigma, 0.25)
-    assert np.abs(th - full).max() < 0.02
+    _check_inference(th, p, x, mu, sigma, 0.25)
+    # Diagnostic only (not the acceptance check): the same rounding points
+    # written out in FP64 agree far more closely, which says the kernel rounds
+    # where it is meant to.
+    assert np.quantile(np.abs(th - mlp.forward_bf16(p, x, mu, sigma, 0.25)), 0.99) <= 1e-5
+
+
+def test_trained_network_on_real_features_matches_fp64(gpu):
+    """The shipped network on the features of a clustered box (computed by
+    the oracle on the CPU), against the FP64 network."""
+    bh = gpu
+    from paper_0909_0541_amd import learned
+    net = learned.ThetaNet.load(learned.DEFAULT_NET)
+    p = net.params.cpu().numpy().astype(np.float64)
+    mu, sigma = net.mu.cpu().numpy(), net.sigma.cpu().numpy()
+    pos, mass = inputs.clustered(30000, 21, n_halos=40)[:2]
+    t = oracle.Tree(pos, mass)
+    t.groups(64)
+    x = all_features(t, 1e-4).astype(np.float32)
+    c = bh.Context()
+    for shift in (-1.0, 0.0, 0.5):
+        th = c.mlp_infer(net.params, net.mu, net.sigma, _f32(x), shift=shift).cpu().numpy().astype(np.float64)
+        _check_inference(th, p, x, mu, sigma, shift)
 
 
 @pytest.mark.parametrize("batch", [1, 333, 2048])
