@@ -4,20 +4,28 @@
 One step = the whole hot path over one synthetic particle set already
 resident in HBM: root cube, Morton keys, radix sort, tree topology and
 moments, groups, the group walk writing the interaction lists, and the FP32
-force sum.  Default workload: clustered box, N = 2,097,152 (30% uniform + 70%
-in 512 Plummer halos), eps = 1e-4, n_crit = 256.
+force sum.  Default workload: clustered box, N = 4,194,304 (30% uniform + 70%
+in 2048 Plummer halos), eps = 1e-4, n_crit = 256: the learned-vs-fixed theta
+configuration.
 
 Before timing, theta is bisected until the RMS relative force error against
-FP64 direct summation on a seeded sample of 4096 particles is 1e-3 (+-3%).
+FP64 direct summation on a seeded sample of 4096 particles is 1e-3 (+-0.3%),
+and the network's output shift likewise for the learned mode (fixed theta is
+the fallback when the network's output is not finite or misses the target).
 Prints one JSON line.  value = tree-force interactions per second of whole
-steps at that theta (sum over members of list length - 1, divided by the
-step time).  Beside it: particles/s; the learned per-group theta at the same
-error (its output shift bisected the same way, features + network in the
-step); the quadrupole option and Peano-Hilbert order at the same error; the
-neighbour search with SPH densities at 64 neighbours per particle; the
-per-particle walk at the same error; the workload's own theta of 0.6; the
-roofline of the dominant kernel (the force sum, FP32 VALU); and the FP64 CPU
-oracle's throughput.
+fixed-theta steps at that theta (sum over members of list length - 1,
+divided by the step time), each step one HIP graph replay.  Beside it:
+particles/s; the learned per-group theta at the same error, its step
+(features, probe walk and inference included) replayed as a graph the same
+way and timed in alternation with the fixed step; interactions of both modes
+interpolated to exactly 1e-3; both modes' RMS on a held-out judge sample; the
+2M clustered box in the same two modes; 20 leapfrog steps of the 8M box with
+learned theta (energy drift); the quadrupole option and Peano-Hilbert order
+at the same error; the neighbour search with SPH densities at 64 neighbours
+per particle; the per-particle walk at the same error; the 64-system batch;
+the roofline of the dominant kernel (the force sum, FP32 VALU); and the FP64
+CPU oracle: its throughput, its own RMS against direct summation, and the
+GPU's deviation from it.
 """
 from __future__ import annotations
 
@@ -37,18 +45,14 @@ if ROOT not in sys.path:
 METRIC = "tree-force interactions/s and particles/s at 1e-3 RMS force error, learned vs fixed θ"
 FP32_VALU_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
 FLOPS_PER_INTERACTION = 20      # 3 sub, 3 FMA (r^2), rsqrt, 3 mul, 3 FMA (acc), 1 add (pot)
+HELDOUT_SEED = 54321            # a second judge sample, not used by any calibration
 
 
 # HBM traffic of the force kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs
-# of this script (bytes per interaction, scaled by the counters' reading of a
-# device copy of known size), valid only for the kernel source it was taken on.
-TRAFFIC = {
-    # clustered box, 2,097,152 particles, theta 0.4203125 (the 1e-3 RMS theta):
-    # FETCH_SIZE 2830548.1 KiB x 1.99987 (a 512 MiB device copy reads as
-    # 262160.69 KiB) + WRITE_SIZE 145878.8 KiB x 1.0 (the copy writes 524288 KiB)
-    "clustered_2m": {"theta": 0.4203125, "bytes_per_launch": 5945973442,
-                     "k_force_sha256": "62fa39ed51d4b632e2aa53196c44a7abed544f7f661602e52b7600e59dfb1141"},
-}
+# of this script (bytes per launch, scaled by the counters' reading of a
+# device copy of known size), valid only for the kernel source and theta it
+# was taken on.
+TRAFFIC = {}
 
 
 def traffic_for(workload, theta):
@@ -67,10 +71,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="clustered_2m")
+    ap.add_argument("--workload", default="clustered_4m")
     ap.add_argument("--n", type=int, default=None, help="override the particle count")
     ap.add_argument("--judge-sample", type=int, default=4096)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle's tree sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--waves-per-cu", type=int, default=None)
     ap.add_argument("--theta", type=float, default=None,
@@ -82,58 +86,23 @@ def parse():
                     help="lower end of the theta bisections (tighter targets need smaller theta)")
     ap.add_argument("--theta-net", default=os.path.join(ROOT, "paper_0909_0541_amd", "theta_net.npz"),
                     help="trained per-group theta network (the learned leg is skipped when missing)")
+    ap.add_argument("--rounds", type=int, default=3,
+                    help="alternating rounds of fixed and learned graph replays for their time ratio")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-particle", action="store_true", help="skip the per-particle walk A/B leg")
     ap.add_argument("--no-quadrupole", action="store_true", help="skip the quadrupole A/B leg")
     ap.add_argument("--no-neighbors", action="store_true", help="skip the neighbour-search leg")
     ap.add_argument("--no-hilbert", action="store_true", help="skip the Peano-Hilbert order A/B leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-systems leg")
+    ap.add_argument("--no-2m", action="store_true", help="skip the 2M clustered leg")
+    ap.add_argument("--no-leapfrog", action="store_true", help="skip the 8M leapfrog leg")
+    ap.add_argument("--leapfrog-steps", type=int, default=20)
     ap.add_argument("--curve", type=int, default=0, choices=(0, 1),
                     help="key order of the headline step: 0 Morton (default), 1 Peano-Hilbert (for counter runs)")
-    ap.add_argument("--no-batch", action="store_true", help="skip the batched-systems leg")
     ap.add_argument("--copy-check-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the timed steps, "
                          "as the reference kernel that scales HBM byte counters")
     return ap.parse_args()
-
-
-def cpu_baseline(pos, mass, w, total_interactions, target_s):
-    """The FP64 oracle on the host: full tree build and grouping, then the
-    walk + force sum for a seeded random sample of groups sized to about
-    target_s seconds; whole-job throughput is extrapolated from the sample."""
-    import numpy as np
-
-    import oracle
-
-    t0 = time.perf_counter()
-    tree = oracle.Tree(pos, mass)
-    G = tree.groups(w.n_crit)
-    t_build = time.perf_counter() - t0
-    order = np.random.default_rng(0).permutation(G)
-    k = max(8, G // 500)
-    t0 = time.perf_counter()
-    pilot = tree.forces(w.eps, w.theta, groups=order[:k])
-    dt = time.perf_counter() - t0
-    rate = max(pilot["interactions"], 1) / max(dt, 1e-6)
-    want = max(1.0, target_s - dt) * rate
-    # extend the sample until it holds about `want` interactions
-    frac = min(1.0, want / max(total_interactions, 1))
-    k2 = int(min(G, max(k, round(frac * G))))
-    t0 = time.perf_counter()
-    out = tree.forces(w.eps, w.theta, groups=order[:k2])
-    t_force = time.perf_counter() - t0
-    sample_inter = max(out["interactions"], 1)
-    t_job = t_build + t_force * total_interactions / sample_inter
-    return {
-        "value": total_interactions / t_job,
-        "unit": "interactions/s",
-        "cores": oracle.num_threads(),
-        "kind": "oracle",
-        "sample": (f"FP64 oracle: full tree build + grouping of all {pos.shape[0]} particles "
-                   f"({t_build:.2f} s), walk + force for {k2} of {G} groups chosen at random "
-                   f"({sample_inter} interactions, {t_force:.2f} s); whole job extrapolated by "
-                   f"interaction count"),
-        "cpu_model": _cpu_model(),
-    }
 
 
 def _cpu_model():
@@ -145,6 +114,114 @@ def _cpu_model():
     except OSError:
         pass
     return "unknown"
+
+
+def _rel_rms(a, ref):
+    import numpy as np
+    n = np.linalg.norm(ref, axis=1)
+    n = np.where(n > 0, n, np.inf)
+    return float(np.sqrt(np.mean((np.linalg.norm(a - ref, axis=1) / n) ** 2)))
+
+
+def _deviation(gpu_acc, gpu_pot, ref, sel):
+    """GPU against the oracle on the particles sel: relative vector deviation
+    |a_gpu - a_orc| / |a_orc| (max, 99.9th percentile), and the fraction of
+    particles inside the per-component parity bound (1e-5 of |a_orc|, or of
+    the sum of term magnitudes where the resultant cancels)."""
+    import numpy as np
+    a = gpu_acc[sel]
+    r = ref["acc"][sel]
+    an = np.linalg.norm(r, axis=1)
+    rel = np.linalg.norm(a - r, axis=1) / np.where(an > 0, an, np.inf)
+    comp = np.abs(a - r).max(axis=1)
+    prel = np.abs(gpu_pot[sel] - ref["pot"][sel]) / np.abs(ref["pot"][sel])
+    return {"particles": int(sel.shape[0]), "max_rel": float(rel.max()),
+            "p999_rel": float(np.quantile(rel, 0.999)),
+            "within_bar": float(np.mean(comp <= 1e-5 * np.maximum(an, ref["acc_abs"][sel]))),
+            "pot_max_rel": float(prel.max())}
+
+
+def cpu_baseline(pos, mass, w, theta, total_interactions, target_s, judge_idx, gpu, learned_run=None):
+    """The FP64 oracle on the host.
+
+    Timed: the full tree build and grouping, the walk + force sum for the
+    groups that hold the judge's particles plus further groups drawn at
+    random until the sample is about target_s seconds of work (whole-job
+    throughput extrapolated by interaction count), and FP64 direct summation
+    for the judge's particles.  Reported with it: the oracle tree's own RMS
+    error against that direct summation, and the GPU's deviation from the
+    oracle on every member of the sampled groups (fixed theta; with
+    learned_run = (theta_g, acc, pot) also the learned step against the
+    oracle with the same per-group theta)."""
+    import numpy as np
+
+    import oracle
+
+    gpu_acc, gpu_pot = gpu
+    t0 = time.perf_counter()
+    tree = oracle.Tree(pos, mass)
+    G = tree.groups(w.n_crit)
+    t_build = time.perf_counter() - t0
+    first, count, _, _ = tree.group_info()
+    _, perm = tree.sorted()
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(perm.shape[0])
+    jg = np.unique(np.searchsorted(first, inv[judge_idx], side="right") - 1)
+    t0 = time.perf_counter()
+    out = tree.forces(w.eps, theta, groups=jg)
+    t_judge = time.perf_counter() - t0
+    rate = max(out["interactions"], 1) / max(t_judge, 1e-6)
+    rest = np.setdiff1d(np.arange(G), jg)
+    extra = np.random.default_rng(0).permutation(rest)
+    want = max(0.0, target_s - t_judge - t_build) * rate
+    mean_per_group = max(out["interactions"], 1) / max(jg.shape[0], 1)
+    k = int(min(extra.shape[0], want / mean_per_group))
+    t_extra, inter_extra = 0.0, 0
+    if k > 0:
+        t0 = time.perf_counter()
+        o2 = tree.forces(w.eps, theta, groups=extra[:k])
+        t_extra = time.perf_counter() - t0
+        inter_extra = o2["interactions"]
+        m = ~np.isnan(o2["acc"][:, 0])
+        out["acc"][m], out["pot"][m], out["acc_abs"][m] = o2["acc"][m], o2["pot"][m], o2["acc_abs"][m]
+    sample_inter = max(out["interactions"] + inter_extra, 1)
+    t_force = t_judge + t_extra
+    t_job = t_build + t_force * total_interactions / sample_inter
+    t0 = time.perf_counter()
+    a_dir, _ = oracle.direct(pos, mass, w.eps, idx=judge_idx)
+    t_direct = time.perf_counter() - t0
+    sel = np.flatnonzero(~np.isnan(out["acc"][:, 0]))
+    res = {
+        "value": total_interactions / t_job,
+        "unit": "interactions/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"FP64 oracle: full tree build + grouping of all {pos.shape[0]} particles ({t_build:.2f} s); "
+                   f"walk + force for the {jg.shape[0]} groups holding the {judge_idx.shape[0]} judge particles "
+                   f"and {k} more of the {G} groups chosen at random ({sample_inter} interactions, "
+                   f"{t_force:.2f} s); whole job extrapolated by interaction count"),
+        "cpu_model": _cpu_model(),
+        "oracle_rms_force_error": _rel_rms(out["acc"][judge_idx], a_dir),
+        "gpu_rms_vs_oracle_direct": _rel_rms(gpu_acc[judge_idx], a_dir),
+        "gpu_vs_oracle": _deviation(gpu_acc, gpu_pot, out, sel),
+        "sampled_direct": {"particles": int(judge_idx.shape[0]), "seconds": t_direct,
+                           "pairs_per_s": judge_idx.shape[0] * pos.shape[0] / t_direct},
+    }
+    if learned_run is not None:
+        tg, lacc, lpot = learned_run
+        t0 = time.perf_counter()
+        ol = tree.forces(w.eps, theta, theta_g=tg, groups=jg)
+        res["learned"] = {"oracle_rms_force_error": _rel_rms(ol["acc"][judge_idx], a_dir),
+                          "gpu_rms_vs_oracle_direct": _rel_rms(lacc[judge_idx], a_dir),
+                          "gpu_vs_oracle": _deviation(lacc, lpot, ol, np.flatnonzero(~np.isnan(ol["acc"][:, 0]))),
+                          "seconds": time.perf_counter() - t0}
+    # full direct summation at the small Plummer configuration (8192 particles)
+    from paper_0909_0541_amd import inputs
+    p8, m8, _ = inputs.plummer(8192, 1, with_vel=False)
+    t0 = time.perf_counter()
+    oracle.direct(p8, m8, 1.0 / 256.0)
+    res["direct_plummer_8k_s"] = time.perf_counter() - t0
+    return res
 
 
 def batch_leg(args):
@@ -177,7 +254,7 @@ def batch_leg(args):
 def particle_leg(args, ctx, judge, dpos, dmass, w, line):
     """The paper's own GPU form as an A/B: every particle walks the tree by
     itself and sums on the way (no groups, no lists); theta bisected to the
-    same RMS error; the step is the tree build plus that walk."""
+    same RMS error (within 3%); the step is the tree build plus that walk."""
     import torch
 
     from paper_0909_0541_amd import learned
@@ -192,14 +269,14 @@ def particle_leg(args, ctx, judge, dpos, dmass, w, line):
         acc, _ = step(th)
         return judge.rms(acc)
 
-    theta, r = learned.bisect(rms_of, 0.2, 1.0, args.target_rms)
+    theta, r = learned.bisect(rms_of, 0.2, 1.0, args.target_rms, rel_tol=0.03, iters=12)
     for _ in range(max(args.warmup, 1)):
         step(theta)
     torch.cuda.synchronize()
     ctx.get_stats()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    steps = max(1, min(args.steps, 5))
+    steps = max(1, min(args.steps, 3))
     e0.record()
     for _ in range(steps):
         step(theta)
@@ -247,16 +324,18 @@ def variant_leg(args, judge, dpos, dmass, w, line, inter_ref, step, **opts):
         gst = g.get_stats()
         if not gst.error_flags and gst.interactions == st.interactions and torch.equal(g._graph_io[2], v.acc):
             ms, mode = ms_g, "graph"
-        del g
+        g.close()
     except (RuntimeError, bh.BHError):
         pass
-    return {"options": opts, "theta": theta, "rms_force_error": judge.rms(v.acc), "ms_per_step": ms,
-            "step_mode": mode, "eager_ms_per_step": ms_eager, "interactions_per_step": st.interactions,
-            "interactions_per_s": st.interactions / (ms * 1e-3), "particles_per_s": n / (ms * 1e-3),
-            "stage_ms": stage, "max_list": st.max_list, "groups": st.n_groups,
-            "interactions_vs_default": st.interactions / inter_ref,
-            "particles_per_s_vs_default": (n / (ms * 1e-3)) / line["particles_per_s"],
-            "step": step}
+    res = {"options": opts, "theta": theta, "rms_force_error": judge.rms(v.acc), "ms_per_step": ms,
+           "step_mode": mode, "eager_ms_per_step": ms_eager, "interactions_per_step": st.interactions,
+           "interactions_per_s": st.interactions / (ms * 1e-3), "particles_per_s": n / (ms * 1e-3),
+           "stage_ms": stage, "max_list": st.max_list, "groups": st.n_groups,
+           "interactions_vs_default": st.interactions / inter_ref,
+           "particles_per_s_vs_default": (n / (ms * 1e-3)) / line["particles_per_s"],
+           "step": step}
+    vctx.close()
+    return res
 
 
 FP64_VALU_PEAK_TFLOPS = 78.6    # MI355X published FP64 vector peak
@@ -280,8 +359,6 @@ def neighbor_leg(args, dpos, dmass, w):
     # the search's own groups: smaller groups test fewer candidate pairs per
     # member (64 measured best on this machine; 256 tests 2.2x as many pairs)
     c.make_groups(NEIGHBOR_NCRIT)
-    cnt = torch.empty(n, dtype=torch.int32, device="cuda")
-    rho = torch.empty(n, dtype=torch.float64, device="cuda")
     for _ in range(max(args.warmup, 1)):
         c.neighbors(h, count=True, rho=True)
     torch.cuda.synchronize()
@@ -301,15 +378,136 @@ def neighbor_leg(args, dpos, dmass, w):
     kms = st.t_neighbor_ms / max(st.n_neighbor_calls, 1)
     achieved = FLOPS_PER_NEIGHBOR_TEST * st.neighbor_tests / (kms * 1e-3) / 1e12
     cn = c.neighbors(h, count=True)[0].cpu()
+    c.close()
     return {"workload": w.name, "n": n, "n_target": 64, "n_crit": NEIGHBOR_NCRIT, "ms_per_call": ms, "kernel_ms": kms,
             "neighbor_pairs": st.neighbor_pairs, "pair_tests": st.neighbor_tests,
             "pairs_per_s": st.neighbor_pairs / (ms * 1e-3), "tests_per_s": st.neighbor_tests / (ms * 1e-3),
             "particles_per_s": n / (ms * 1e-3),
             "median_neighbors": float(cn.median().item()), "max_neighbors": int(cn.max().item()),
-            "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "roofline": {"bound": "latency", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved / FP64_VALU_PEAK_TFLOPS, "kernel": "k_neighbors",
-                         "flops_per_test": FLOPS_PER_NEIGHBOR_TEST},
+                         "flops_per_test": FLOPS_PER_NEIGHBOR_TEST,
+                         "note": "bound by the latency of node reads (walk) and LDS broadcasts (pair loop); "
+                                 "the FP64 rate is given for scale, not as the bound"},
             "step": "neighbour counts and SPH densities of every particle on a built tree and groups"}
+
+
+def _stages(st, theta=False):
+    per = lambda t, k: t / max(k, 1)
+    out = {"build": per(st.t_build_ms, st.n_build_calls), "groups": per(st.t_groups_ms, st.n_groups_calls),
+           "walk": per(st.t_walk_ms, st.n_walk_calls), "force": per(st.t_force_ms, st.n_force_calls)}
+    if theta:
+        out["theta"] = per(st.t_theta_ms, st.n_theta_calls)
+    return out
+
+
+def equal_error(args, w, dpos, dmass, net, headline: bool):
+    """Fixed and learned theta on one particle set at the same RMS error.
+
+    Both are calibrated on the judge sample (bisection to within 0.3%, plus
+    interactions interpolated to exactly the target from the bisections);
+    each mode's whole step is captured as a HIP graph, its replay checked bit
+    for bit against the eager step, and the two replays are timed in
+    alternating rounds.  Returns (report, objects the caller may reuse)."""
+    import numpy as np
+    import torch
+
+    from paper_0909_0541_amd import autotune, bh, learned
+
+    n = dpos.shape[0]
+    ctx = bh.Context(timing=True, waves_per_cu=args.waves_per_cu, curve=args.curve)
+    judge = learned.Judge(ctx, dpos, dmass, w.eps, args.judge_sample)
+    heldout = learned.Judge(ctx, dpos, dmass, w.eps, args.judge_sample, seed=HELDOUT_SEED)
+    fixed = learned.Stepper(ctx, dpos, dmass, w.eps, w.n_crit)
+    cal = None
+    if args.target_rms > 0 and args.theta is None:
+        cal = learned.calibrate(ctx, dpos, dmass, w.eps, w.n_crit, None if args.no_learned else net, judge,
+                                args.target_rms, theta_lo=args.theta_lo)
+        theta = cal.theta
+    else:
+        theta = w.theta if args.theta is None else args.theta
+    ms_eager, st = learned.timed_steps(fixed, args.steps, args.warmup, theta=theta)
+    inter = st.interactions
+    rep = {"n": n, "theta": theta, "rms_force_error": judge.rms(fixed.acc),
+           "heldout_rms_force_error": heldout.rms(fixed.acc), "interactions_per_step": inter,
+           "stage_ms": _stages(st), "eager_ms_per_step": ms_eager, "groups": st.n_groups, "cells": st.n_cells,
+           "max_list": st.max_list}
+    off = np.array([0, n], dtype=np.int64)
+    gf = bh.Context(waves_per_cu=args.waves_per_cu, curve=args.curve)
+    gf.graph_capture(off, dpos, dmass, w.n_crit, [w.eps], [theta])
+    graph_error = None
+    ms_fixed = autotune.time_graph(gf, args.steps, args.warmup)
+    gst = gf.get_stats()
+    if gst.error_flags or gst.interactions != inter or not torch.equal(gf._graph_io[2], fixed.acc):
+        graph_error = (f"replay differs from the eager step (flags {gst.error_flags}, "
+                       f"interactions {gst.interactions} vs {inter})")
+        ms_fixed = ms_eager
+    rep["ms_per_step"] = ms_fixed
+    rep["step_mode"] = "graph" if graph_error is None else f"eager ({graph_error})"
+    rep["interactions_per_s"] = inter / (ms_fixed * 1e-3)
+    rep["particles_per_s"] = n / (ms_fixed * 1e-3)
+    if cal is not None:
+        rep["calibration"] = {"target_rms": args.target_rms, "theta": theta, "rms": cal.fixed_rms,
+                              "band": 0.003, "evaluations": len(cal.fixed_history),
+                              "search": f"bisection over theta in [{args.theta_lo}, 1.0]",
+                              "interactions_at_target": learned.at_target(cal.fixed_history, args.target_rms)}
+    keep = {"ctx": ctx, "judge": judge, "fixed": fixed, "theta": theta, "stats": st, "learned": None}
+    if cal is not None and net is not None and not args.no_learned:
+        lr = {"mode": cal.mode, "fallback_reason": cal.reason, "shift": cal.shift,
+              "calibration_rms": cal.learned_rms, "evaluations": len(cal.learned_history),
+              "interactions_at_target": learned.at_target(cal.learned_history, args.target_rms)}
+        if cal.mode == "learned":
+            lstep = learned.Stepper(ctx, dpos, dmass, w.eps, w.n_crit, net)
+            ms_le, st_l = learned.timed_steps(lstep, args.steps, args.warmup, theta=theta, shift=cal.shift)
+            gl = bh.Context(waves_per_cu=args.waves_per_cu, curve=args.curve)
+            gl.graph_capture_learned(off, dpos, dmass, w.n_crit, [w.eps], [theta], net.params, net.mu, net.sigma,
+                                     shift=cal.shift)
+            ms_l = autotune.time_graph(gl, args.steps, args.warmup)
+            lst = gl.get_stats()
+            lmode = "graph"
+            if lst.error_flags or lst.interactions != st_l.interactions or not torch.equal(gl._graph_io[2], lstep.acc):
+                lmode, ms_l = "eager (replay differs from the eager step)", ms_le
+            # alternating rounds: fixed replay, learned replay, ... (drifts of
+            # clock or temperature then hit both modes alike)
+            rounds_f, rounds_l = [], []
+            if lmode == "graph" and graph_error is None:
+                for _ in range(max(args.rounds, 1)):
+                    rounds_f.append(autotune.time_graph(gf, args.steps, 1))
+                    rounds_l.append(autotune.time_graph(gl, args.steps, 1))
+            ratio = (float(np.median(np.array(rounds_f) / np.array(rounds_l))) if rounds_f
+                     else ms_fixed / ms_l)
+            tg = lstep.theta_g[:st_l.n_groups].cpu().numpy()
+            lr.update({
+                "rms_force_error": judge.rms(lstep.acc), "heldout_rms_force_error": heldout.rms(lstep.acc),
+                "ms_per_step": ms_l, "step_mode": lmode, "eager_ms_per_step": ms_le,
+                "interactions_per_step": st_l.interactions,
+                "interactions_per_s": st_l.interactions / (ms_l * 1e-3), "particles_per_s": n / (ms_l * 1e-3),
+                "stage_ms": _stages(st_l, theta=True), "theta_fallback_groups": st_l.n_theta_fallback,
+                "theta_mean": float(tg.mean()), "theta_min": float(tg.min()), "theta_max": float(tg.max()),
+                "interactions_saved": 1.0 - st_l.interactions / inter,
+                "alternating_ms": {"fixed": rounds_f, "learned": rounds_l},
+                "particles_per_s_vs_fixed": ratio,
+                "step": "one HIP graph replay: tree build, groups, features + probe walk + inference, "
+                        "list walk, force sum"})
+            fa, la = rep["calibration"]["interactions_at_target"], lr["interactions_at_target"]
+            if fa and la:
+                lr["interactions_at_target_vs_fixed"] = la / fa
+            keep["learned"] = (lstep, gl)
+        rep["learned"] = lr
+    keep["graph"] = gf
+    return rep, keep
+
+
+def leapfrog_leg(args):
+    """Time integration of the 8M clustered box (halo velocities): learned
+    theta calibrated to the target RMS at t = 0 (fixed theta as fallback),
+    then kick-drift-kick steps with the tree rebuilt every step."""
+    from paper_0909_0541_amd import simulate
+    out = simulate.run("clustered_8m", steps=args.leapfrog_steps, dt=1e-4, target_rms=args.target_rms,
+                       learned_theta=os.path.exists(args.theta_net) and not args.no_learned,
+                       theta_net=args.theta_net, judge_sample=args.judge_sample, every=10)
+    out.pop("energy", None)
+    return out
 
 
 def main():
@@ -321,26 +519,16 @@ def main():
     import numpy as np
     import torch
 
-    from paper_0909_0541_amd import bh, inputs, learned
+    from paper_0909_0541_amd import inputs, learned
 
     torch.cuda.set_device(0)
+    net = None
+    if os.path.exists(args.theta_net) and not args.no_learned:
+        net = learned.ThetaNet.load(args.theta_net)
     pos, mass, _, w = inputs.make_workload(args.workload, n=args.n)
     n = pos.shape[0]
     dpos = torch.as_tensor(pos, device="cuda")
     dmass = torch.as_tensor(mass, device="cuda")
-    ctx = bh.Context(timing=True, waves_per_cu=args.waves_per_cu, curve=args.curve)
-    judge = learned.Judge(ctx, dpos, dmass, w.eps, args.judge_sample)
-    fixed = learned.Stepper(ctx, dpos, dmass, w.eps, w.n_crit)
-
-    calib = None
-    theta = w.theta if args.theta is None else args.theta
-    if args.target_rms > 0 and args.theta is None:
-        def rms_of(th):
-            fixed(theta=th)
-            return judge.rms(fixed.acc)
-        theta, r = learned.bisect(rms_of, args.theta_lo, 1.0, args.target_rms)
-        calib = {"target_rms": args.target_rms, "theta": theta, "rms": r, "band": 0.03,
-                 "search": f"bisection over theta in [{args.theta_lo}, 1.0]"}
 
     if args.copy_check_mib > 0:
         nb = args.copy_check_mib << 20
@@ -351,39 +539,15 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    def stages(st):
-        per = lambda t, k: t / max(k, 1)
-        return {"build": per(st.t_build_ms, st.n_build_calls), "groups": per(st.t_groups_ms, st.n_groups_calls),
-                "walk": per(st.t_walk_ms, st.n_walk_calls), "force": per(st.t_force_ms, st.n_force_calls)}
-
-    ms_eager, st = learned.timed_steps(fixed, args.steps, args.warmup, theta=theta)
-    stage = stages(st)
-    rms = judge.rms(fixed.acc)
-    inter = st.interactions
-    # The timed step: the same whole step (build, groups, list walk, force
-    # sum) captured once as a HIP graph and replayed, which takes the host's
-    # launch work and the force call's list-pool check off the GPU's path.
-    # (A replay that does not reproduce the eager step's forces bit for bit
-    # is not reported: the eager time is then the step time.)
-    from paper_0909_0541_amd import autotune
-    step_mode, graph_error = "graph", None
-    try:
-        gctx = bh.Context(waves_per_cu=args.waves_per_cu, curve=args.curve)
-        gctx.graph_capture(np.array([0, n], dtype=np.int64), dpos, dmass, w.n_crit, [w.eps], [theta])
-        ms_per_step = autotune.time_graph(gctx, args.steps, args.warmup)
-        gst = gctx.get_stats()
-        if gst.error_flags or gst.interactions != inter or not torch.equal(gctx._graph_io[2], fixed.acc):
-            raise RuntimeError(f"replay differs from the eager step (flags {gst.error_flags}, "
-                               f"interactions {gst.interactions} vs {inter})")
-        del gctx
-    except (RuntimeError, bh.BHError) as e:
-        step_mode, graph_error, ms_per_step = "eager", str(e), ms_eager
-    value = inter / (ms_per_step * 1e-3)
-    t_force = stage["force"]
+    rep, keep = equal_error(args, w, dpos, dmass, net, headline=True)
+    ctx, judge, theta, st = keep["ctx"], keep["judge"], keep["theta"], keep["stats"]
+    inter = rep["interactions_per_step"]
+    ms_per_step = rep["ms_per_step"]
+    t_force = rep["stage_ms"]["force"]
     achieved = FLOPS_PER_INTERACTION * inter / (t_force * 1e-3) / 1e12
     line = {
         "metric": METRIC,
-        "value": value,
+        "value": inter / (ms_per_step * 1e-3),
         "unit": "interactions/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -396,74 +560,88 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "description": w.description, "n": n, "eps": w.eps, "theta": theta,
                    "workload_theta": w.theta, "n_crit": w.n_crit,
-                   "theta_mode": "fixed" if calib is None else "fixed, bisected to the target RMS force error",
+                   "theta_mode": ("fixed, bisected to the target RMS force error" if "calibration" in rep
+                                  else "fixed"),
                    "key_order": "Peano-Hilbert" if args.curve else "Morton"},
-        "particles_per_s": n / (ms_per_step * 1e-3),
-        "step": ("one HIP graph replay: tree build, groups, list walk, force sum" if step_mode == "graph"
-                 else f"eager calls (graph replay not used: {graph_error})"),
-        "eager": {"ms_per_step": ms_eager, "interactions_per_s": inter / (ms_eager * 1e-3),
+        "particles_per_s": rep["particles_per_s"],
+        "step": ("one HIP graph replay: tree build, groups, list walk, force sum" if rep["step_mode"] == "graph"
+                 else rep["step_mode"]),
+        "eager": {"ms_per_step": rep["eager_ms_per_step"], "interactions_per_s": inter / (rep["eager_ms_per_step"] * 1e-3),
                   "step": "the same calls issued one by one (the force call waits for the walk to check its "
                           "list pools)"},
         "interactions_per_step": inter,
         "interactions_per_particle": inter / n,
-        "rms_force_error": rms,
+        "rms_force_error": rep["rms_force_error"],
+        "heldout_rms_force_error": rep["heldout_rms_force_error"],
         "judge_sample": int(judge.idx.shape[0]),
-        "theta_calibration": calib,
-        "groups": st.n_groups,
-        "cells": st.n_cells,
-        "max_list": st.max_list,
-        "stage_ms": stage,
+        "theta_calibration": rep.get("calibration"),
+        "groups": rep["groups"],
+        "cells": rep["cells"],
+        "max_list": rep["max_list"],
+        "stage_ms": rep["stage_ms"],
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": traffic_for(w.name, theta),
                      "kernel": "k_force_lists", "flops_per_interaction": FLOPS_PER_INTERACTION},
         "force_kernel_interactions_per_s": inter / (t_force * 1e-3),
-        "walk_plus_force_interactions_per_s": inter / ((stage["walk"] + t_force) * 1e-3),
+        "walk_plus_force_interactions_per_s": inter / ((rep["stage_ms"]["walk"] + t_force) * 1e-3),
     }
-    if calib is not None and not args.no_learned and os.path.exists(args.theta_net):
-        net = learned.ThetaNet.load(args.theta_net)
-        lstep = learned.Stepper(ctx, dpos, dmass, w.eps, w.n_crit, net)
-
-        def rms_shift(sh):
-            lstep(shift=sh)
-            return judge.rms(lstep.acc)
-        sh, r = learned.bisect(rms_shift, -8.0, 8.0, args.target_rms)
-        if abs(r / args.target_rms - 1) <= 0.03 or r <= args.target_rms:
-            ms_l, st_l = learned.timed_steps(lstep, args.steps, args.warmup, shift=sh)
-            tg = lstep.theta_g[:st_l.n_groups].cpu().numpy()
-            line["learned"] = {
-                "shift": sh, "rms_force_error": judge.rms(lstep.acc), "ms_per_step": ms_l,
-                "interactions_per_step": st_l.interactions, "interactions_per_s": st_l.interactions / (ms_l * 1e-3),
-                "particles_per_s": n / (ms_l * 1e-3), "stage_ms": stages(st_l),
-                "theta_mean": float(tg.mean()), "theta_min": float(tg.min()), "theta_max": float(tg.max()),
-                "interactions_saved": 1.0 - st_l.interactions / inter,
-                "particles_per_s_vs_fixed": (n / (ms_l * 1e-3)) / line["particles_per_s"]}
-        else:
-            line["learned"] = {"fallback_to_fixed": True, "shift": sh, "rms_force_error": r}
-    if calib is not None and abs(theta - w.theta) > 1e-12:
+    if "learned" in rep:
+        line["learned"] = rep["learned"]
+    fixed_acc = keep["fixed"].acc
+    gpu_fixed = (fixed_acc.double().cpu().numpy(), keep["fixed"].pot.double().cpu().numpy())
+    learned_run = None
+    if keep["learned"] is not None:
+        lstep, _ = keep["learned"]
+        G = st.n_groups
+        learned_run = (lstep.theta_g[:G].double().cpu().numpy(), lstep.acc.double().cpu().numpy(),
+                       lstep.pot.double().cpu().numpy())
+    if "calibration" in rep and abs(theta - w.theta) > 1e-12:
+        fixed = keep["fixed"]
         ms2, st2 = learned.timed_steps(fixed, args.steps, args.warmup, theta=w.theta)
-        s2 = stages(st2)
+        s2 = _stages(st2)
         line["at_workload_theta"] = {
             "theta": w.theta, "rms_force_error": judge.rms(fixed.acc), "ms_per_step": ms2,
             "interactions_per_s": st2.interactions / (ms2 * 1e-3), "particles_per_s": n / (ms2 * 1e-3),
             "interactions_per_step": st2.interactions, "stage_ms": s2,
             "force_kernel_tflops": FLOPS_PER_INTERACTION * st2.interactions / (s2["force"] * 1e-3) / 1e12}
-    if calib is not None and not args.no_quadrupole:
+    keep["graph"].close()
+    if keep["learned"] is not None:
+        keep["learned"][1].close()
+    if "calibration" in rep and not args.no_quadrupole:
         line["quadrupole"] = variant_leg(
             args, judge, dpos, dmass, w, line, inter,
             "tree build with second moments, groups, list walk, force sum with quadrupole terms", quadrupole=True)
-    if calib is not None and not args.no_hilbert:
+    if "calibration" in rep and not args.no_hilbert:
         line["hilbert"] = variant_leg(
             args, judge, dpos, dmass, w, line, inter,
             "the same step with Peano-Hilbert keys (particles, children and groups in curve order)", curve=1)
     if not args.no_neighbors:
         line["neighbors"] = neighbor_leg(args, dpos, dmass, w)
-    if calib is not None and not args.no_particle:
+    if "calibration" in rep and not args.no_particle:
         line["per_particle"] = particle_leg(args, ctx, judge, dpos, dmass, w, line)
+    ctx.close()
+    del keep
+    if not args.no_2m and w.name != "clustered_2m" and args.n is None and args.theta is None:
+        p2, m2, _, w2 = inputs.make_workload("clustered_2m")
+        d2p, d2m = torch.as_tensor(p2, device="cuda"), torch.as_tensor(m2, device="cuda")
+        r2, k2 = equal_error(args, w2, d2p, d2m, net, headline=False)
+        for k in ("graph",):
+            k2[k].close()
+        if k2["learned"] is not None:
+            k2["learned"][1].close()
+        k2["ctx"].close()
+        r2["workload"] = w2.name
+        line["clustered_2m"] = r2
+        del d2p, d2m, k2
     if not args.no_batch:
         line["batch"] = batch_leg(args)
+    if not args.no_leapfrog and args.n is None:
+        torch.cuda.empty_cache()
+        line["leapfrog_8m"] = leapfrog_leg(args)
     if not args.no_cpu_baseline:
         w_cpu = dataclasses.replace(w, theta=theta)
-        line["cpu_baseline"] = cpu_baseline(pos, mass, w_cpu, inter, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(pos, mass, w_cpu, theta, inter, args.cpu_seconds, judge.idx,
+                                            gpu_fixed, learned_run)
     print(json.dumps(line), flush=True)
 
 

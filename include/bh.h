@@ -95,6 +95,10 @@ typedef struct {
   double t_neighbor_ms;     /* bh_neighbors calls */
   int64_t neighbor_pairs;   /* last bh_neighbors: neighbours found (sum of the counts) */
   int64_t neighbor_tests;   /* last bh_neighbors: member-candidate pairs whose distance was tested */
+  double t_theta_ms;        /* bh_group_theta calls (features, probe walk, inference) */
+  int32_t n_theta_calls;
+  int32_t n_theta_fallback; /* last force call: groups whose per-group theta was NaN (walked with the
+                               call's theta) */
 } bh_stats;
 
 typedef struct {
@@ -192,7 +196,9 @@ bh_status bh_make_groups(bh_ctx *ctx, int32_t n_crit, int64_t *n_groups_out);
  *   eps > 0 (eps^2 must be a normal FP32 number), theta in [0, 1]
  *   (theta = 0 opens every cell: exact direct summation).
  *   theta_group device FP32 [n_groups], nullable: per-group theta overriding
- *   theta (values in [0, 1]; out-of-range values raise an error flag).
+ *   theta (values in [0, 1]; a NaN stands for "no value": that group walks
+ *   with theta and is counted in stats.n_theta_fallback; other values
+ *   outside [0, 1] raise an error flag).
  *   acc device FP32 [n][3], pot device FP32 [n]: input order.
  * Two kernels (the interaction-list method of Sec. 3.2): every group walks
  * the tree once with the FP64 opening test and writes its list to HBM as FP32
@@ -336,8 +342,24 @@ bh_status bh_mlp_infer(bh_ctx *ctx, const bh_mlp *net, int64_t rows, const float
 
 /* Features and theta of the current groups in one asynchronous call (the
  * features go to a context-owned buffer).  theta device FP32, room for
- * max(n, 1) values; pass it as theta_group to bh_compute_forces. */
+ * max(n, 1) values; pass it as theta_group to bh_compute_forces.  A row
+ * whose network output is not a number gives theta NaN, which the force call
+ * replaces by its own theta for that group (the fixed-theta fallback).
+ * With timing enabled, stats.t_theta_ms sums these calls. */
 bh_status bh_group_theta(bh_ctx *ctx, const bh_mlp *net, const double *eps_sys, float shift, float *theta);
+
+/* bh_graph_capture for a step with learned theta: the captured step is tree
+ * build, groups, bh_group_theta (features, probe walk, inference at the
+ * given shift, into theta_group), then the list walk and force sum with
+ * theta_group; theta_sys is the fixed theta of groups whose network output
+ * is NaN.  theta_group device FP32, room for max(n, 1) values, rewritten by
+ * every replay; net's arrays must stay in place while the capture is used.
+ * Otherwise as bh_graph_capture (same checks, same eager first step, same
+ * replay rules).  Synchronises. */
+bh_status bh_graph_capture_learned(bh_ctx *ctx, int32_t n_systems, const int64_t *offsets, const double *pos,
+                                   const double *mass, int32_t n_crit, const double *eps_sys,
+                                   const double *theta_sys, const bh_mlp *net, float shift, float *theta_group,
+                                   float *acc, float *pot);
 
 /* FP32 loss and gradient of a training batch: loss = sum_b w_b (theta_b -
  * target_b)^2 / sum_b w_b with theta_b the network output at shift 0 (FP32

@@ -41,7 +41,8 @@ class _Stats(C.Structure):
                 ("n_split_groups", C.c_int32), ("n_segments", C.c_int32), ("n_split_levels", C.c_int32),
                 ("n_walk_attempts", C.c_int32), ("t_particle_ms", C.c_double), ("n_particle_calls", C.c_int32),
                 ("n_neighbor_calls", C.c_int32), ("t_neighbor_ms", C.c_double), ("neighbor_pairs", C.c_int64),
-                ("neighbor_tests", C.c_int64)]
+                ("neighbor_tests", C.c_int64), ("t_theta_ms", C.c_double), ("n_theta_calls", C.c_int32),
+                ("n_theta_fallback", C.c_int32)]
 
 
 class _Mlp(C.Structure):
@@ -83,6 +84,8 @@ def load():
         "bh_leapfrog": ([vp, i64, vp, vp, vp, C.c_double, C.c_double, i32, C.c_double, i32, vp, vp], C.c_int),
         "bh_get_stats": ([vp, C.POINTER(_Stats)], C.c_int),
         "bh_graph_capture": ([vp, i32, vp, vp, vp, i32, vp, vp, vp, vp, vp], C.c_int),
+        "bh_graph_capture_learned": ([vp, i32, vp, vp, vp, i32, vp, vp, C.POINTER(_Mlp), C.c_float, vp, vp, vp],
+                                     C.c_int),
         "bh_graph_launch": ([vp], C.c_int),
         "bh_group_features": ([vp, vp, vp], C.c_int),
         "bh_mlp_infer": ([vp, C.POINTER(_Mlp), i64, vp, C.c_float, vp], C.c_int),
@@ -154,6 +157,9 @@ class Stats:
     t_neighbor_ms: float
     neighbor_pairs: int
     neighbor_tests: int
+    t_theta_ms: float
+    n_theta_calls: int
+    n_theta_fallback: int
 
 
 class Context:
@@ -326,6 +332,41 @@ class Context:
         self.n, self.n_systems = n, ns
         self._graph_io = (pos, mass, acc, pot, theta_group)  # keep the captured buffers alive
         return acc, pot
+
+    def graph_capture_learned(self, offsets, pos: torch.Tensor, mass: torch.Tensor, n_crit: int, eps_sys,
+                              theta_sys, params, mu, sigma, shift: float = 0.0, theta_group=None, acc=None,
+                              pot=None):
+        """Record one whole step with the network's per-group theta (features,
+        probe walk and inference inside the graph); theta_sys is the fixed
+        theta of groups whose network output is NaN.  Returns (acc, pot,
+        theta_group), which every graph_launch() rewrites."""
+        import numpy as np
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        ns = len(off) - 1
+        n = int(off[-1])
+        e = np.ascontiguousarray(np.broadcast_to(np.asarray(eps_sys, dtype=np.float64), (ns,)))
+        t = np.ascontiguousarray(np.broadcast_to(np.asarray(theta_sys, dtype=np.float64), (ns,)))
+        _dev(pos, torch.float64, (n, 3), "pos")
+        _dev(mass, torch.float64, (n,), "mass")
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if acc is None:
+            acc = torch.empty((n, 3), dtype=torch.float32, device=dev)
+        if pot is None:
+            pot = torch.empty((n,), dtype=torch.float32, device=dev)
+        if theta_group is None:
+            theta_group = torch.empty((max(n, 1),), dtype=torch.float32, device=dev)
+        _dev(acc, torch.float32, (n, 3), "acc")
+        _dev(pot, torch.float32, (n,), "pot")
+        _dev(theta_group, torch.float32, (max(n, 1),), "theta_group")
+        net = self._net(params, mu, sigma)
+        self._check(self._L.bh_graph_capture_learned(self._h, ns, off.ctypes.data_as(C.c_void_p), _ptr(pos),
+                                                     _ptr(mass), int(n_crit), e.ctypes.data_as(C.c_void_p),
+                                                     t.ctypes.data_as(C.c_void_p), C.byref(net), float(shift),
+                                                     _ptr(theta_group), _ptr(acc), _ptr(pot)))
+        self.n, self.n_systems = n, ns
+        # keep the captured buffers (and the network) alive
+        self._graph_io = (pos, mass, acc, pot, theta_group, params, mu, sigma)
+        return acc, pot, theta_group
 
     def graph_launch(self):
         self._check(self._L.bh_graph_launch(self._h))

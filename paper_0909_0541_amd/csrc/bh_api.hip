@@ -406,7 +406,7 @@ void bh_destroy(bh_ctx *c) {
   if (c->stage) (void)hipHostFree(c->stage);
   if (c->split_host) (void)hipHostFree(c->split_host);
   if (c->stage_event) (void)hipEventDestroy(c->stage_event);
-  Timer *ts[] = {&c->t_build, &c->t_groups, &c->t_walk, &c->t_force, &c->t_particle, &c->t_neighbor};
+  Timer *ts[] = {&c->t_build, &c->t_groups, &c->t_walk, &c->t_force, &c->t_particle, &c->t_neighbor, &c->t_theta};
   for (Timer *t : ts)
     for (hipEvent_t e : t->ev) (void)hipEventDestroy(e);
   delete c;
@@ -819,27 +819,41 @@ bh_status bh_compute_forces_particle_batch(bh_ctx *c, const double *eps_sys, con
   return particle_common(c, eps_sys, theta_sys, acc, pot);
 }
 
-bh_status bh_graph_capture(bh_ctx *c, int32_t n_systems, const int64_t *offsets, const double *pos,
-                           const double *mass, int32_t n_crit, const double *eps_sys, const double *theta_sys,
-                           const float *theta_group, float *acc, float *pot) {
-  if (!c) return BH_EINVAL;
-  c->err.clear();
+static bh_status theta_common(bh_ctx *c, const bh_mlp *net, const double *eps_sys, float shift, float *theta);
+
+// One whole step (build, groups, [per-group theta from the network], walk
+// and force sum); the learned variant writes theta_out and walks with it.
+static bh_status step_common(bh_ctx *c, int32_t n_systems, const int64_t *offsets, const double *pos,
+                             const double *mass, int32_t n_crit, const double *eps_sys, const double *theta_sys,
+                             const float *theta_group, const bh_mlp *net, float shift, float *theta_out, float *acc,
+                             float *pot) {
+  bh_status st = build_common(c, n_systems, offsets, pos, mass);
+  if (!st) st = bh_make_groups(c, n_crit, nullptr);
+  if (!st && net) st = theta_common(c, net, eps_sys, shift, theta_out);
+  if (!st) st = forces_common(c, eps_sys, theta_sys, net ? theta_out : theta_group, acc, pot);
+  return st;
+}
+
+static bh_status capture_common(bh_ctx *c, int32_t n_systems, const int64_t *offsets, const double *pos,
+                                const double *mass, int32_t n_crit, const double *eps_sys, const double *theta_sys,
+                                const float *theta_group, const bh_mlp *net, float shift, float *theta_out,
+                                float *acc, float *pot) {
   if (n_systems < 1 || n_systems > 65536 || !offsets || !eps_sys || !theta_sys)
     return fail(c, BH_EINVAL, "bad graph capture arguments");
   if (offsets[0] != 0) return fail(c, BH_EINVAL, "offsets[0] must be 0");
   for (int s = 0; s < n_systems; ++s)
     if (offsets[s + 1] < offsets[s]) return fail(c, BH_EINVAL, "offsets must be non-decreasing");
   if (n_crit < 1 || n_crit > BH_MAX_NCRIT) return fail(c, BH_EINVAL, "n_crit must be in [1, 256]");
+  if (net && !theta_out) return fail(c, BH_EINVAL, "theta_group must not be NULL");
   // 1. one eager step sizes every buffer and checks the arguments
-  bh_status st = build_common(c, n_systems, offsets, pos, mass);
-  if (!st) st = bh_make_groups(c, n_crit, nullptr);
-  if (!st) st = forces_common(c, eps_sys, theta_sys, theta_group, acc, pot);
+  bh_status st = step_common(c, n_systems, offsets, pos, mass, n_crit, eps_sys, theta_sys, theta_group, net, shift,
+                             theta_out, acc, pot);
   if (!st) st = bh_sync(c);
   if (st) return st;
   // 2. headroom in the list pools for replays on moved particles
   c->far_cap += c->far_cap / 4;
   c->near_cap += c->near_cap / 4;
-  st = forces_common(c, eps_sys, theta_sys, theta_group, acc, pot);
+  st = forces_common(c, eps_sys, theta_sys, net ? theta_out : theta_group, acc, pot);
   if (!st) st = bh_sync(c);
   if (st) return st;
   // 3. record the same launches on a capture stream
@@ -856,9 +870,8 @@ bh_status bh_graph_capture(bh_ctx *c, int32_t n_systems, const int64_t *offsets,
   c->capturing = true;
   st = hip_check(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
   if (!st) {
-    bh_status sr = build_common(c, n_systems, offsets, pos, mass);
-    if (!sr) sr = bh_make_groups(c, n_crit, nullptr);
-    if (!sr) sr = forces_common(c, eps_sys, theta_sys, theta_group, acc, pot);
+    bh_status sr = step_common(c, n_systems, offsets, pos, mass, n_crit, eps_sys, theta_sys, theta_group, net, shift,
+                               theta_out, acc, pot);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->stream, &g);
     c->capturing = false;
@@ -876,6 +889,26 @@ bh_status bh_graph_capture(bh_ctx *c, int32_t n_systems, const int64_t *offsets,
   c->capturing = false;
   c->stream = saved;
   return st;
+}
+
+bh_status bh_graph_capture(bh_ctx *c, int32_t n_systems, const int64_t *offsets, const double *pos,
+                           const double *mass, int32_t n_crit, const double *eps_sys, const double *theta_sys,
+                           const float *theta_group, float *acc, float *pot) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  return capture_common(c, n_systems, offsets, pos, mass, n_crit, eps_sys, theta_sys, theta_group, nullptr, 0.0f,
+                        nullptr, acc, pot);
+}
+
+bh_status bh_graph_capture_learned(bh_ctx *c, int32_t n_systems, const int64_t *offsets, const double *pos,
+                                   const double *mass, int32_t n_crit, const double *eps_sys,
+                                   const double *theta_sys, const bh_mlp *net, float shift, float *theta_group,
+                                   float *acc, float *pot) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (!net) return fail(c, BH_EINVAL, "net must not be NULL");
+  return capture_common(c, n_systems, offsets, pos, mass, n_crit, eps_sys, theta_sys, nullptr, net, shift,
+                        theta_group, acc, pot);
 }
 
 bh_status bh_graph_launch(bh_ctx *c) {
@@ -909,6 +942,7 @@ bh_status bh_get_stats(bh_ctx *c, bh_stats *out) {
     out->n_segments = c->last_segments;
     out->n_split_levels = c->last_depth;
     out->n_walk_attempts = c->last_attempts;
+    out->n_theta_fallback = d.theta_fallback;
   }
   out->t_build_ms = timer_take(c->t_build, &out->n_build_calls);
   out->t_groups_ms = timer_take(c->t_groups, &out->n_groups_calls);
@@ -916,6 +950,7 @@ bh_status bh_get_stats(bh_ctx *c, bh_stats *out) {
   out->t_force_ms = timer_take(c->t_force, &out->n_force_calls);
   out->t_particle_ms = timer_take(c->t_particle, &out->n_particle_calls);
   out->t_neighbor_ms = timer_take(c->t_neighbor, &out->n_neighbor_calls);
+  out->t_theta_ms = timer_take(c->t_theta, &out->n_theta_calls);
   if (c->have_neighbors) {
     out->neighbor_pairs = (int64_t)d.nb_pairs;
     out->neighbor_tests = (int64_t)d.nb_tests;
@@ -1055,9 +1090,7 @@ bh_status bh_mlp_infer(bh_ctx *c, const bh_mlp *net, int64_t rows, const float *
   return hip_check(c, hipGetLastError(), "kernel launch (inference)");
 }
 
-bh_status bh_group_theta(bh_ctx *c, const bh_mlp *net, const double *eps_sys, float shift, float *theta) {
-  if (!c) return BH_EINVAL;
-  c->err.clear();
+static bh_status theta_common(bh_ctx *c, const bh_mlp *net, const double *eps_sys, float shift, float *theta) {
   bh_status st = check_net(c, net);
   if (st) return st;
   if (!isfinite(shift)) return fail(c, BH_EINVAL, "shift must be finite");
@@ -1065,12 +1098,22 @@ bh_status bh_group_theta(bh_ctx *c, const bh_mlp *net, const double *eps_sys, fl
   const int64_t cap = std::max<int64_t>(c->n, 1);
   st = ensure(c, c->mlp_feat, sizeof(float) * BH_MLP_FEATURES * (size_t)cap, "features");
   if (st) return st;
+  st = timer_start(c, c->t_theta);
+  if (st) return st;
   st = features_common(c, eps_sys, P<float>(c->mlp_feat));
   if (st || c->n == 0) return st;
   // rows = -1: the kernel reads the group count on the device
   mlp_infer_device(net->params, net->mu, net->sigma, P<float>(c->mlp_feat), -1, cap, P<DevInfo>(c->info), shift,
                    theta, c->stream);
+  st = timer_stop(c, c->t_theta);
+  if (st) return st;
   return hip_check(c, hipGetLastError(), "kernel launch (inference)");
+}
+
+bh_status bh_group_theta(bh_ctx *c, const bh_mlp *net, const double *eps_sys, float shift, float *theta) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  return theta_common(c, net, eps_sys, shift, theta);
 }
 
 bh_status bh_mlp_grad(bh_ctx *c, const bh_mlp *net, int32_t batch, const float *x, const float *target,

@@ -64,6 +64,8 @@ struct DevInfo {
   int32_t n_items;        // force work items (group, member block)
   unsigned long long nb_pairs;  // neighbour search: neighbours found (sum of the counts)
   unsigned long long nb_tests;  // neighbour search: candidate pairs whose distance was tested
+  int32_t theta_fallback;  // groups of the last walk whose per-group theta was NaN (walked with the call's theta)
+  int32_t pad0;
   // Counters that every wave of a kernel updates, each in a 128-byte line of
   // its own (atomics on one line serialise behind each other).
   alignas(128) int32_t queue2;  // force work queue head
@@ -235,7 +237,7 @@ struct bh_ctx {
   bool stage_event_used = false;
   uint64_t *sorted_keys = nullptr;    // the key buffer holding the sorted keys
 
-  bh::Timer t_build, t_groups, t_walk, t_force, t_particle, t_neighbor;
+  bh::Timer t_build, t_groups, t_walk, t_force, t_particle, t_neighbor, t_theta;
 };
 
 namespace bh {

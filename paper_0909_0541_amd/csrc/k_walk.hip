@@ -260,6 +260,12 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) v
       cen[k] = __dmul_rn(__dadd_rn(blo[k], bhi[k]), 0.5);
     }
     double theta = a.theta_group ? (double)a.theta_group[g] : a.par[gs].theta;
+    if (isnan(theta)) {
+      // no usable per-group value (e.g. a network whose output is not a
+      // number): this group walks with the call's theta
+      theta = a.par[gs].theta;
+      if (lane == 0 && !is_task) atomicAdd(&a.info->theta_fallback, 1);
+    }
     if (!(theta >= 0.0 && theta <= 1.0)) {
       if (lane == 0 && !is_task) atomicOr(&a.info->err, kErrTheta);
       theta = (theta > 1.0) ? 1.0 : 0.0;

@@ -208,7 +208,8 @@ def rms_error(acc, didx, a_dir, a_dir_norm) -> float:
     return float(math.sqrt(np.mean(rel * rel)))
 
 
-def bisect(f, lo: float, hi: float, target: float, increasing: bool = True, rel_tol: float = 0.03, iters: int = 16):
+def bisect(f, lo: float, hi: float, target: float, increasing: bool = True, rel_tol: float = 0.003,
+           iters: int = 24):
     """x in [lo, hi] with f(x) within rel_tol of target (f monotone on
     average); returns (x, f(x)) of the closest evaluation."""
     best = None
@@ -337,3 +338,89 @@ def equal_error(ctx: bh.Context, dpos, dmass, eps: float, n_crit: int, net: Thet
                    "particles_per_s_learned_over_fixed": out["learned"]["particles_per_s"] /
                    out["fixed"]["particles_per_s"]}
     return out
+
+
+class Recorder:
+    """Wraps a step and a judge: every evaluation records (parameter, judge
+    RMS, interactions) so that a calibration can also be read at exactly the
+    target error by interpolation between the evaluations that bracket it."""
+
+    def __init__(self, step, judge, key: str):
+        self.step, self.judge, self.key = step, judge, key
+        self.history = []
+
+    def __call__(self, x):
+        self.step(**{self.key: x})
+        r = self.judge.rms(self.step.acc)
+        self.history.append((float(x), r, int(self.step.ctx.get_stats().interactions)))
+        return r
+
+
+def at_target(history, target: float):
+    """Interactions at exactly the target RMS: log-linear interpolation
+    between the closest evaluations below and above the target (None when
+    the evaluations do not bracket it)."""
+    below = [h for h in history if h[1] <= target]
+    above = [h for h in history if h[1] > target]
+    if not below or not above:
+        return None
+    b = max(below, key=lambda h: h[1])
+    a = min(above, key=lambda h: h[1])
+    if a[1] == b[1] or b[2] <= 0 or a[2] <= 0:
+        return float(b[2])
+    t = (math.log(target) - math.log(b[1])) / (math.log(a[1]) - math.log(b[1]))
+    return float(math.exp(math.log(b[2]) + t * (math.log(a[2]) - math.log(b[2]))))
+
+
+@dataclass
+class Calibration:
+    """Outcome of calibrating both modes to one RMS target on a judge sample."""
+    mode: str                 # "learned", or "fixed" when the learned mode is not used
+    theta: float              # fixed theta at the target (also the theta of NaN groups)
+    shift: float | None       # network output shift at the target (learned mode)
+    fixed_rms: float
+    learned_rms: float | None
+    reason: str               # why the fixed path was taken ("" for learned)
+    fixed_history: list
+    learned_history: list
+
+
+def calibrate(ctx: bh.Context, dpos, dmass, eps: float, n_crit: int, net: ThetaNet | None, judge: Judge,
+              target: float, theta_lo: float = 0.3, rel_tol: float = 0.003) -> Calibration:
+    """Fixed theta, then the network's shift, bisected to the target RMS.
+    The learned mode is taken only when the network gives a finite theta for
+    every group and its calibrated error meets the target (within rel_tol);
+    otherwise fixed theta is the fallback."""
+    fixed = Stepper(ctx, dpos, dmass, eps, n_crit)
+    fr = Recorder(fixed, judge, "theta")
+    theta, r_fixed = bisect(fr, theta_lo, 1.0, target, rel_tol=rel_tol)
+    base = dict(theta=theta, fixed_rms=r_fixed, fixed_history=fr.history)
+    if net is None:
+        return Calibration("fixed", shift=None, learned_rms=None, reason="no network", learned_history=[], **base)
+    lstep = Stepper(ctx, dpos, dmass, eps, n_crit, net)
+    lstep(theta=theta, shift=0.0)
+    G = ctx.get_stats().n_groups
+    if not bool(torch.isfinite(lstep.theta_g[:G]).all()):
+        return Calibration("fixed", shift=None, learned_rms=None, reason="network output not finite",
+                           learned_history=[], **base)
+    lr = Recorder(_Fixed(lstep, theta), judge, "shift")
+    sh, r = bisect(lr, -8.0, 8.0, target, rel_tol=rel_tol)
+    if r > target * (1.0 + rel_tol):
+        return Calibration("fixed", shift=sh, learned_rms=r, reason="the network misses the error target",
+                           learned_history=lr.history, **base)
+    return Calibration("learned", shift=sh, learned_rms=r, reason="", learned_history=lr.history, **base)
+
+
+class _Fixed:
+    """A learned Stepper called with its fallback theta held fixed."""
+
+    def __init__(self, step: Stepper, theta: float):
+        self.step, self.theta = step, theta
+        self.ctx = step.ctx
+
+    @property
+    def acc(self):
+        return self.step.acc
+
+    def __call__(self, shift: float = 0.0):
+        self.step(theta=self.theta, shift=shift)
