@@ -105,6 +105,14 @@ def parse():
     return ap.parse_args()
 
 
+_T0 = time.perf_counter()
+
+
+def progress(msg):
+    """One line on stderr as each part of the run ends (stdout keeps the one JSON line)."""
+    print(f"bench: {msg} ({time.perf_counter() - _T0:.1f} s)", file=sys.stderr, flush=True)
+
+
 def _cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -539,7 +547,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    progress(f"{w.name}: inputs on the device")
     rep, keep = equal_error(args, w, dpos, dmass, net, headline=True)
+    progress(f"{w.name}: fixed and learned calibrated and timed")
     ctx, judge, theta, st = keep["ctx"], keep["judge"], keep["theta"], keep["stats"]
     inter = rep["interactions_per_step"]
     ms_per_step = rep["ms_per_step"]
@@ -611,14 +621,18 @@ def main():
         line["quadrupole"] = variant_leg(
             args, judge, dpos, dmass, w, line, inter,
             "tree build with second moments, groups, list walk, force sum with quadrupole terms", quadrupole=True)
+        progress("quadrupole leg done")
     if "calibration" in rep and not args.no_hilbert:
         line["hilbert"] = variant_leg(
             args, judge, dpos, dmass, w, line, inter,
             "the same step with Peano-Hilbert keys (particles, children and groups in curve order)", curve=1)
+        progress("Peano-Hilbert leg done")
     if not args.no_neighbors:
         line["neighbors"] = neighbor_leg(args, dpos, dmass, w)
+        progress("neighbour leg done")
     if "calibration" in rep and not args.no_particle:
         line["per_particle"] = particle_leg(args, ctx, judge, dpos, dmass, w, line)
+        progress("per-particle leg done")
     ctx.close()
     del keep
     if not args.no_2m and w.name != "clustered_2m" and args.n is None and args.theta is None:
@@ -632,16 +646,20 @@ def main():
         k2["ctx"].close()
         r2["workload"] = w2.name
         line["clustered_2m"] = r2
+        progress("2M leg done")
         del d2p, d2m, k2
     if not args.no_batch:
         line["batch"] = batch_leg(args)
+        progress("batch leg done")
     if not args.no_leapfrog and args.n is None:
         torch.cuda.empty_cache()
         line["leapfrog_8m"] = leapfrog_leg(args)
+        progress("8M leapfrog leg done")
     if not args.no_cpu_baseline:
         w_cpu = dataclasses.replace(w, theta=theta)
         line["cpu_baseline"] = cpu_baseline(pos, mass, w_cpu, theta, inter, args.cpu_seconds, judge.idx,
                                             gpu_fixed, learned_run)
+        progress("CPU oracle baseline done")
     print(json.dumps(line), flush=True)
 
 
