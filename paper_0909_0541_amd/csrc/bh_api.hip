@@ -722,12 +722,15 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
   F.pot = pot;
   F.info = P<DevInfo>(c->info);
   F.order = P<int32_t>(c->item_order);
+  F.xstart = P<int32_t>(c->order_hist) + (order_hist_bytes() / sizeof(int32_t) - 16);
+  F.glist = P<int32_t>(c->glist);
   F.segs = S.segs;
   F.seg_order = S.order;
   F.gsegfirst = S.gsegfirst;
   F.pbase = S.pbase;
   F.psum = split ? P<double>(c->psum) : nullptr;
-  item_order_device(F, (int64_t)icap, P<int32_t>(c->order_hist), P<int32_t>(c->item_order), c->stream);
+  item_order_device(F, P<int32_t>(c->item_n), P<int32_t>(c->item_off), (int64_t)gcap, P<int32_t>(c->order_hist),
+                    P<int32_t>(c->item_order), c->stream);
   st = timer_start(c, c->t_force);
   if (st) return st;
   force_lists_device(F, fgrid, c->stream);

@@ -72,6 +72,7 @@ struct DevInfo {
   alignas(128) int32_t far_chunks;   // runs of kChunkRun list chunks taken (may exceed the pool: then it is the need)
   alignas(128) int32_t near_chunks;
   alignas(128) int32_t xq[8 * kLineInts];  // walk queue heads, one per XCD: xq[x * kLineInts]
+  alignas(128) int32_t fq[8 * kLineInts];  // force queue heads, one per XCD: fq[x * kLineInts]
 };
 
 // Interaction lists: chunks of kFarChunk far entries (float4 x - c_g, m) and
@@ -425,7 +426,9 @@ struct ForceArgs {
   float *pot;
   DevInfo *info;
   const int32_t *items;  // [n_items][2] group, member block (+ 256 x (segment + 1) for a split group)
-  const int32_t *order;  // queue position -> item (longest first)
+  const int32_t *order;  // queue position -> item: eight per-XCD queues, longest group first
+  const int32_t *xstart; // [9]: first queue position of each XCD's queue, then the item count
+  const int32_t *glist;  // [G] list length of each group (all segments)
   // split groups: segments sorted by (group, key), the first sorted segment
   // of each group, and the partial sums of each segment's members
   const Segment *segs;
@@ -440,7 +443,8 @@ void force_items_device(const int32_t *ginfo, const int32_t *gsplit, const int32
                         DevInfo *info, int64_t cap, int32_t *nblk, int32_t *off, int32_t *items, void *scan_tmp,
                         int32_t *mean_list, hipStream_t s);
 void force_lists_device(const ForceArgs &a, int grid, hipStream_t s);
-void item_order_device(const ForceArgs &f, int64_t cap, int32_t *hist, int32_t *order, hipStream_t s);
+void item_order_device(const ForceArgs &f, const int32_t *nblk, const int32_t *item_off, int64_t gcap, int32_t *hist,
+                       int32_t *order, hipStream_t s);
 int force_lists_blocks_per_cu(bool quad);
 void reset_list_counters(DevInfo *info, hipStream_t s);
 

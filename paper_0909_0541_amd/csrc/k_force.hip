@@ -2,7 +2,9 @@
 // coordinates, partial sums folded into FP64).
 //
 // Work items are (group, block of 64 members, or the group's remainder); a
-// persistent grid of single-wave workgroups pulls items from an atomic queue.
+// persistent grid of single-wave workgroups pulls items from eight atomic
+// queues, one per XCD, which hold the items of each group next to each other
+// (so that the blocks of a group read its list through the same L2).
 // A block of m members uses R lane partitions of W = 64/R >= m lanes, one
 // member per lane;
 // partition `part` takes list entries part, part + R, ...  With R = 1 every
@@ -248,11 +250,24 @@ __global__ __launch_bounds__(kWave) void k_force_lists(ForceArgs a, const float4
                                                        const int32_t *__restrict__ far_slot,
                                                        const float4 *__restrict__ qpack) {
   const int lane = lane_id();
-  const int T = a.info->n_items;
+  // workgroups are dealt to the XCDs round robin: this wave's XCD queue
+  // first, then the others
+  const int xcd = blockIdx.x & 7;
+  int tried = 0;
   for (;;) {
-    const int qi = take_one(&a.info->queue2, lane);
-    if (qi >= T) break;
-    const int it = a.order ? __builtin_amdgcn_readfirstlane(a.order[qi]) : qi;
+    int it = -1;
+    while (tried < 8) {
+      // (a provably uniform queue index keeps the take a single atomic)
+      const int x = __builtin_amdgcn_readfirstlane((xcd + tried) & 7);
+      const int s0 = a.xstart[x], s1 = a.xstart[x + 1];
+      const int q = take_one(&a.info->fq[x * kLineInts], lane);
+      if (s0 + q < s1) {
+        it = __builtin_amdgcn_readfirstlane(a.order[s0 + q]);
+        break;
+      }
+      ++tried;
+    }
+    if (it < 0) break;
     const int g = items[2 * it], iv = items[2 * it + 1];
     const int blk = iv & 255, segl = iv >> 8;
     const int gf = a.ginfo[3 * g], gc = a.ginfo[3 * g + 1], gs = a.ginfo[3 * g + 2];

@@ -113,7 +113,10 @@ __global__ void k_reset_force_counters(DevInfo *info) {
     info->max_list = 0;
     info->theta_fallback = 0;
     info->err &= ~kErrPool;
-    for (int x = 0; x < 8; ++x) info->xq[x * kLineInts] = 0;
+    for (int x = 0; x < 8; ++x) {
+      info->xq[x * kLineInts] = 0;
+      info->fq[x * kLineInts] = 0;
+    }
   }
 }
 

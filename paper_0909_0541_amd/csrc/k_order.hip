@@ -1,14 +1,20 @@
-// Longest-first processing order for the persistent force kernel.
+// Processing order of the persistent force kernel: eight queues, one per
+// XCD, longest first, with the member blocks of a group next to each other.
 //
-// The kernel pulls work items from an atomic queue; when a few long items are
-// pulled last, the grid idles while they finish.  Ordering the queue by cost,
-// longest first, bounds that tail (list scheduling).  The order is a counting
-// sort over integer cost bins (descending): cost bin = (far entries + 2 near
-// entries) / lane partitions / 64, the passes one item makes over its lists.
-// Each block ranks one tile of items per bin with LDS atomics and takes one
-// run of positions per non-empty bin from the global cursors.  The order
-// within a bin does not change any result: every item computes its own
-// outputs.
+// A group's member blocks (and the segments of a split group) all read the
+// same interaction list.  When they run at the same time on the same XCD,
+// the first block to reach a stretch of the list brings it into that XCD's
+// L2 and the others find it there; spread over the chip, every block fetches
+// the list from HBM again.  So every group is given to one XCD (the group
+// index modulo 8: neighbouring groups have similar lists, so each XCD gets
+// an even share of the work), and its items occupy consecutive places of
+// that XCD's queue, where consecutive waves take them.  Within a queue the
+// groups are ordered by cost, longest first, which bounds the tail of the
+// launch (list scheduling); a wave whose queue is empty takes from the
+// others.  The order is a counting sort of the groups over (XCD, cost bin),
+// each group weighted by its item count; cost bin = list length / lane
+// partitions of its first block / 128.  The order within a bin does not
+// change any result: every item computes its own outputs.
 #include <algorithm>
 
 #include "bh_device.h"
@@ -17,94 +23,116 @@ namespace bh {
 
 namespace {
 
-constexpr int kBins = 1024;
-constexpr int kTile = 2048;  // items ranked per block
+constexpr int kBins = 512;
+constexpr int kXcd = 8;
+constexpr int kKeys = kXcd * kBins;
+constexpr int kTile = 2048;  // groups ranked per block
 
-__device__ __forceinline__ int item_key(const ForceArgs &f, int64_t it) {
-  const int g = f.items[2 * it], iv = f.items[2 * it + 1];
-  const int blk = iv & 255, segl = iv >> 8;
+__device__ __forceinline__ int group_key(const ForceArgs &f, int g) {
   const int gc = f.ginfo[3 * g + 1];
-  const int m = min(gc - blk * kWave, kWave);  // full blocks of 64, then the remainder
+  const int m = min(gc, kWave);  // the first block (full, or the whole small group)
   int R = 1;
   while (R < kWave && m * (2 * R) <= kWave) R *= 2;
-  int64_t len;
-  if (segl == 0) {
-    len = (int64_t)f.glists[4 * g + 1] + 2 * (int64_t)f.glists[4 * g + 3];
-  } else {
-    const Segment &sg = f.segs[f.seg_order[f.gsegfirst[g] + segl - 1]];
-    len = (int64_t)sg.fn + 2 * (int64_t)sg.nn;
-  }
-  return (int)min<int64_t>((len / R) >> 6, kBins - 1);
+  const int64_t len = (int64_t)max(f.glist[g], 0);
+  const int bin = (int)min<int64_t>((len / R) >> 7, kBins - 1);
+  return (g & (kXcd - 1)) * kBins + (kBins - 1 - bin);
 }
 
 __global__ void k_order_clear(int32_t *hist) {
-  for (int b = threadIdx.x; b < kBins; b += blockDim.x) hist[b] = 0;
+  for (int b = threadIdx.x; b < kKeys; b += blockDim.x) hist[b] = 0;
 }
 
-__global__ __launch_bounds__(256) void k_order_hist(ForceArgs f, int64_t cap, int32_t *__restrict__ hist) {
-  __shared__ int32_t h[kBins];
-  for (int b = threadIdx.x; b < kBins; b += blockDim.x) h[b] = 0;
+// Item counts per (XCD, bin).
+__global__ __launch_bounds__(256) void k_order_hist(ForceArgs f, const int32_t *__restrict__ nblk, int64_t cap,
+                                                    int32_t *__restrict__ hist) {
+  __shared__ int32_t h[kKeys];
+  for (int b = threadIdx.x; b < kKeys; b += blockDim.x) h[b] = 0;
   __syncthreads();
-  const int64_t n = min<int64_t>(f.info->n_items, cap);
+  const int64_t G = min<int64_t>(f.info->n_groups, cap);
   const int64_t t0 = (int64_t)blockIdx.x * kTile;
-  for (int64_t i = t0 + threadIdx.x; i < n && i < t0 + kTile; i += blockDim.x)
-    atomicAdd(&h[kBins - 1 - item_key(f, i)], 1);
+  for (int64_t g = t0 + threadIdx.x; g < G && g < t0 + kTile; g += blockDim.x)
+    if (nblk[g] > 0) atomicAdd(&h[group_key(f, (int)g)], nblk[g]);
   __syncthreads();
-  for (int b = threadIdx.x; b < kBins; b += blockDim.x)
+  for (int b = threadIdx.x; b < kKeys; b += blockDim.x)
     if (h[b]) atomicAdd(&hist[b], h[b]);
 }
 
-// Exclusive scan of the bins (one block of kBins threads), in place.
-__global__ __launch_bounds__(kBins) void k_order_scan(int32_t *hist) {
-  __shared__ int32_t w[kBins / kWave];
+// Exclusive scan of the bins in place (one block of 1024 threads, kKeys /
+// 1024 bins each); xstart[x] = first queue position of XCD x, xstart[8] the
+// item count.
+__global__ __launch_bounds__(1024) void k_order_scan(int32_t *__restrict__ hist, int32_t *__restrict__ xstart) {
+  constexpr int kPer = kKeys / 1024;
+  __shared__ int32_t w[1024 / kWave];
   const int t = threadIdx.x;
-  const int v = hist[t];
-  const int inc = wave_inclusive_sum(v);
+  int v[kPer], s = 0;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    v[j] = hist[t * kPer + j];
+    s += v[j];
+  }
+  const int inc = wave_inclusive_sum(s);
   if (lane_id() == kWave - 1) w[t / kWave] = inc;
   __syncthreads();
   int off = 0;
   for (int k = 0; k < t / kWave; ++k) off += w[k];
-  hist[t] = off + inc - v;
+  off += inc - s;
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int b = t * kPer + j;
+    if (b % kBins == 0) xstart[b / kBins] = off;
+    hist[b] = off;
+    off += v[j];
+  }
+  if (t == 1023) xstart[kXcd] = off;
 }
 
-__global__ __launch_bounds__(256) void k_order_scatter(ForceArgs f, int64_t cap, int32_t *__restrict__ cursor,
-                                                       int32_t *__restrict__ order) {
+// Each group takes a run of nblk[g] queue places from its bin's cursor and
+// lists its items there in order (item_off[g] + b).
+__global__ __launch_bounds__(256) void k_order_scatter(ForceArgs f, const int32_t *__restrict__ nblk,
+                                                       const int32_t *__restrict__ item_off, int64_t cap,
+                                                       int32_t *__restrict__ cursor, int32_t *__restrict__ order) {
   constexpr int kPer = kTile / 256;
-  __shared__ int32_t cnt[kBins], base[kBins];
-  const int64_t n = min<int64_t>(f.info->n_items, cap);
+  __shared__ int32_t cnt[kKeys], base[kKeys];
+  const int64_t G = min<int64_t>(f.info->n_groups, cap);
   const int64_t t0 = (int64_t)blockIdx.x * kTile;
-  if (t0 >= n) return;
-  for (int b = threadIdx.x; b < kBins; b += blockDim.x) cnt[b] = 0;
+  if (t0 >= G) return;
+  for (int b = threadIdx.x; b < kKeys; b += blockDim.x) cnt[b] = 0;
   __syncthreads();
   int key[kPer], rank[kPer];
 #pragma unroll
   for (int j = 0; j < kPer; ++j) {
-    const int64_t i = t0 + j * 256 + threadIdx.x;
+    const int64_t g = t0 + j * 256 + threadIdx.x;
     key[j] = -1;
-    if (i < n) {
-      key[j] = kBins - 1 - item_key(f, i);
-      rank[j] = atomicAdd(&cnt[key[j]], 1);
+    if (g < G && nblk[g] > 0) {
+      key[j] = group_key(f, (int)g);
+      rank[j] = atomicAdd(&cnt[key[j]], nblk[g]);
     }
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < kBins; b += blockDim.x) base[b] = cnt[b] ? atomicAdd(&cursor[b], cnt[b]) : 0;
+  for (int b = threadIdx.x; b < kKeys; b += blockDim.x) base[b] = cnt[b] ? atomicAdd(&cursor[b], cnt[b]) : 0;
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kPer; ++j)
-    if (key[j] >= 0) order[base[key[j]] + rank[j]] = (int32_t)(t0 + j * 256 + threadIdx.x);
+  for (int j = 0; j < kPer; ++j) {
+    if (key[j] < 0) continue;
+    const int64_t g = t0 + j * 256 + threadIdx.x;
+    const int p = base[key[j]] + rank[j], first = item_off[g];
+    for (int b = 0; b < nblk[g]; ++b) order[p + b] = first + b;
+  }
 }
 
 }  // namespace
 
-size_t order_hist_bytes() { return sizeof(int32_t) * kBins; }
+size_t order_hist_bytes() { return sizeof(int32_t) * (kKeys + 16); }
 
-void item_order_device(const ForceArgs &f, int64_t cap, int32_t *hist, int32_t *order, hipStream_t s) {
-  if (cap <= 0) return;
-  const unsigned grid = (unsigned)((cap + kTile - 1) / kTile);
+void item_order_device(const ForceArgs &f, const int32_t *nblk, const int32_t *item_off, int64_t gcap, int32_t *hist,
+                       int32_t *order, hipStream_t s) {
+  if (gcap <= 0) return;
+  const unsigned grid = (unsigned)((gcap + kTile - 1) / kTile);
+  int32_t *xstart = hist + kKeys;
   k_order_clear<<<1, 256, 0, s>>>(hist);
-  k_order_hist<<<grid, 256, 0, s>>>(f, cap, hist);
-  k_order_scan<<<1, kBins, 0, s>>>(hist);
-  k_order_scatter<<<grid, 256, 0, s>>>(f, cap, hist, order);
+  k_order_hist<<<grid, 256, 0, s>>>(f, nblk, gcap, hist);
+  k_order_scan<<<1, 1024, 0, s>>>(hist, xstart);
+  k_order_scatter<<<grid, 256, 0, s>>>(f, nblk, item_off, gcap, hist, order);
 }
 
 }  // namespace bh
