@@ -274,6 +274,25 @@ bh_status bh_get_stats(bh_ctx *ctx, bh_stats *stats);
 bh_status bh_direct_sampled(bh_ctx *ctx, int64_t n, const double *pos, const double *mass, double eps,
                             int64_t s, const int64_t *idx, double *acc, double *pot);
 
+/* Bytes of the static device array behind bh_direct_sampled_noalloc (one per
+ * device the library runs on, held until the process ends). */
+#define BH_JUDGE_SCRATCH_BYTES (8 << 20)
+
+/* bh_direct_sampled for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, kernels and results (bit for bit) as
+ * bh_direct_sampled, but the FP64 partial sums live in a static device array
+ * of BH_JUDGE_SCRATCH_BYTES per device instead of context-owned memory: the
+ * call allocates nothing.  The partial sums take 32 bytes per sampled
+ * particle and j chunk (a few MiB for any s up to tens of thousands); a
+ * sample whose partial sums would not fit is rejected with BH_EINVAL before
+ * anything is launched.  Every call on one device shares that device's
+ * array: calls that overlap on one device (other contexts or streams) race,
+ * so order them on one stream.  The array's address is looked up once per
+ * device by bh_create (which does allocate); later calls only launch. */
+bh_status bh_direct_sampled_noalloc(bh_ctx *ctx, int64_t n, const double *pos, const double *mass, double eps,
+                                    int64_t s, const int64_t *idx, double *acc, double *pot);
+
 /* ---- time integration (kick-drift-kick leapfrog, FP64 state) ----------- */
 
 /* vel += dt * acc (acc FP32 [n][3] from a force call, vel FP64 [n][3]). */

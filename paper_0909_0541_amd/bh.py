@@ -93,6 +93,7 @@ def load():
         "bh_mlp_grad": ([vp, C.POINTER(_Mlp), i32, vp, vp, vp, vp, vp], C.c_int),
         "bh_mlp_adam": ([vp, vp, vp, vp, vp, i32, i32, C.c_float, C.c_float, C.c_float, C.c_float], C.c_int),
         "bh_direct_sampled": ([vp, i64, vp, vp, dbl, i64, vp, vp, vp], C.c_int),
+        "bh_direct_sampled_noalloc": ([vp, i64, vp, vp, dbl, i64, vp, vp, vp], C.c_int),
         "bh_kick": ([vp, i64, vp, vp, dbl], C.c_int),
         "bh_drift": ([vp, i64, vp, vp, dbl], C.c_int),
         "bh_energy": ([vp, i64, vp, vp, vp, vp], C.c_int),
@@ -387,6 +388,22 @@ class Context:
         pot = torch.empty((s,), dtype=torch.float64, device=pos.device)
         self._check(self._L.bh_direct_sampled(self._h, n, _ptr(pos), _ptr(mass), float(eps), s, _ptr(idx),
                                               _ptr(acc), _ptr(pot)))
+        return acc, pot
+
+    def direct_sampled_noalloc(self, pos: torch.Tensor, mass: torch.Tensor, eps: float, idx: torch.Tensor,
+                               acc: torch.Tensor, pot: torch.Tensor):
+        """The same judge through the entry point that allocates nothing
+        (partial sums in the library's static device array); the caller
+        provides acc [s, 3] and pot [s] (FP64, on the device)."""
+        n = pos.shape[0]
+        _dev(pos, torch.float64, (n, 3), "pos")
+        _dev(mass, torch.float64, (n,), "mass")
+        _dev(idx, torch.int64, None, "idx")
+        s = idx.shape[0]
+        _dev(acc, torch.float64, (s, 3), "acc")
+        _dev(pot, torch.float64, (s,), "pot")
+        self._check(self._L.bh_direct_sampled_noalloc(self._h, n, _ptr(pos), _ptr(mass), float(eps), s, _ptr(idx),
+                                                      _ptr(acc), _ptr(pot)))
         return acc, pot
 
     def kick(self, vel: torch.Tensor, acc: torch.Tensor, dt: float):

@@ -371,6 +371,11 @@ bh_status bh_create(bh_ctx **out, void *stream) {
   if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, c->device) != hipSuccess || clock_khz <= 0)
     clock_khz = 100000;
   c->wait_ticks = (long long)clock_khz * 2000;
+  // the no-allocation judge's static scratch: its address on this device
+  if (judge_scratch_address(c->device, &c->judge_scratch) != hipSuccess || !c->judge_scratch) {
+    delete c;
+    return BH_EHIP;
+  }
   if (hipHostMalloc((void **)&c->info_host, sizeof(DevInfo), 0) != hipSuccess) {
     delete c;
     return BH_ENOMEM;
@@ -975,6 +980,26 @@ bh_status bh_direct_sampled(bh_ctx *c, int64_t n, const double *pos, const doubl
   if (st) return st;
   direct_sampled_device(pos, mass, n, eps, s, idx, acc, pot, P<double>(c->direct_part), chunk, nchunk, c->stream);
   return hip_check(c, hipGetLastError(), "kernel launch (direct)");
+}
+
+bh_status bh_direct_sampled_noalloc(bh_ctx *c, int64_t n, const double *pos, const double *mass, double eps,
+                                    int64_t s, const int64_t *idx, double *acc, double *pot) {
+  if (!c) return BH_EINVAL;
+  c->err.clear();
+  if (n < 0 || s < 0) return fail(c, BH_EINVAL, "negative size");
+  if (s > 0 && (!pos || !mass || !idx || !acc || !pot)) return fail(c, BH_EINVAL, "NULL pointer");
+  if (!(eps >= 0.0) || !isfinite(eps)) return fail(c, BH_EINVAL, "eps must be finite and >= 0");
+  if (s == 0) return BH_OK;
+  int64_t chunk, nchunk;
+  const size_t bytes = direct_part_bytes(n, s, c->num_cu, &chunk, &nchunk);
+  if (bytes > kJudgeScratchBytes)
+    return fail(c, BH_EINVAL, "sample too large for the no-allocation judge: its partial sums need " +
+                                  std::to_string(bytes) + " bytes, the static scratch holds " +
+                                  std::to_string(kJudgeScratchBytes));
+  // every partial-sum row the reduction reads is written by the first kernel:
+  // the scratch needs no clearing
+  direct_sampled_device(pos, mass, n, eps, s, idx, acc, pot, c->judge_scratch, chunk, nchunk, c->stream);
+  return hip_check(c, hipGetLastError(), "kernel launch (direct, no allocation)");
 }
 
 bh_status bh_kick(bh_ctx *c, int64_t n, double *vel, const float *acc, double dt) {

@@ -212,6 +212,7 @@ struct bh_ctx {
   bh::DevBuf par;               // SysParam [nsys]
   bh::DevBuf info;              // DevInfo
   bh::DevBuf direct_part;       // FP64 partial sums of the judge
+  double *judge_scratch = nullptr;  // device address of the static judge scratch on this context's device
   bh::DevBuf energy_part;       // FP64 energy partials
   bh::DevBuf feps;              // FP64 [nsys] softening of the feature call
   bh::DevBuf mlp_work;          // training batch workspace
@@ -450,6 +451,10 @@ void reset_list_counters(DevInfo *info, hipStream_t s);
 
 // k_misc.hip
 size_t direct_part_bytes(int64_t n, int64_t s, int num_cu, int64_t *chunk, int64_t *nchunk);
+// static scratch of the no-allocation judge: its size, and its device address
+// on `device` (looked up once per device with that device current)
+constexpr size_t kJudgeScratchBytes = (size_t)BH_JUDGE_SCRATCH_BYTES;
+hipError_t judge_scratch_address(int device, double **ptr);
 void direct_sampled_device(const double *pos, const double *mass, int64_t n, double eps, int64_t s,
                            const int64_t *idx, double *acc, double *pot, double *part, int64_t chunk,
                            int64_t nchunk, hipStream_t st);

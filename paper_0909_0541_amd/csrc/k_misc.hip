@@ -1,4 +1,6 @@
 // FP64 direct-summation judge (Eq. 1), leapfrog kick/drift and energy sums.
+#include <mutex>
+
 #include "bh_device.h"
 
 namespace bh {
@@ -128,6 +130,28 @@ __global__ void k_energy_final(const double *__restrict__ part, int nb, double *
 }
 
 }  // namespace
+
+// The judge's partial sums for callers that cannot allocate
+// (bh_direct_sampled_noalloc): one static array per device, held until the
+// process ends.  Host code never names it except to look up its device
+// address (judge_scratch_address); every call on a device shares it.
+static __device__ __align__(256) double scratch[kJudgeScratchBytes / sizeof(double)];
+
+hipError_t judge_scratch_address(int device, double **ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double *addr[kMaxDevices] = {};
+  std::lock_guard<std::mutex> lock(mu);
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!addr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = static_cast<double *>(p);
+  }
+  *ptr = addr[device];
+  return hipSuccess;
+}
 
 size_t direct_part_bytes(int64_t n, int64_t s, int num_cu, int64_t *chunk, int64_t *nchunk) {
   // enough j chunks that the grid holds a few blocks per compute unit
