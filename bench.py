@@ -235,7 +235,8 @@ def cpu_baseline(pos, mass, w, theta, total_interactions, target_s, judge_idx, g
 def batch_leg(args):
     """64 independent systems of uneven size (Plummer spheres and clustered
     boxes, N log-uniform in [1024, 262144], theta = 0.7, eps = N^(-1/3)/20) as
-    one captured HIP graph per step, n_crit and waves per CU autotuned."""
+    one captured HIP graph per step, n_crit, waves per CU and the list tile
+    length autotuned."""
     import torch
 
     from paper_0909_0541_amd import autotune, inputs
@@ -250,13 +251,13 @@ def batch_leg(args):
     acc = ctx._graph_io[2]
     n = int(off[-1])
     return {"workload": "batch_64", "systems": int(len(off) - 1), "n": n, "theta": theta,
-            "n_crit": best.n_crit, "waves_per_cu": best.waves_per_cu, "ms_per_step": ms,
+            "n_crit": best.n_crit, "waves_per_cu": best.waves_per_cu, "list_tile": best.list_tile, "ms_per_step": ms,
             "interactions_per_step": st.interactions, "interactions_per_s": st.interactions / (ms * 1e-3),
             "particles_per_s": n / (ms * 1e-3),
             "rms_force_error": autotune.batch_rms(ctx, off, dpos, dmass, eps, acc, sample=args.judge_sample),
             "step": "one HIP graph replay: build of all 64 trees, groups, list walk, force sum",
-            "autotune": [{"n_crit": t.n_crit, "waves_per_cu": t.waves_per_cu, "ms": t.ms_per_step}
-                         for t in trials]}
+            "autotune": [{"n_crit": t.n_crit, "waves_per_cu": t.waves_per_cu, "list_tile": t.list_tile,
+                          "ms": t.ms_per_step} for t in trials]}
 
 
 def particle_leg(args, ctx, judge, dpos, dmass, w, line):

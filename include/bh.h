@@ -130,6 +130,12 @@ typedef struct {
                             0 (default) Morton, bit interleaving; 1 Peano-Hilbert, consecutive
                             cells face-adjacent.  The cells are the same either way; the order,
                             and hence the groups, differ.  Takes effect at the next build. */
+  int32_t list_tile;     /* entries per chunk of a group's far interaction list (its near list uses
+                            chunks of half as many): the walk hands lists to the force sum in these
+                            tiles, and the force sum folds its FP32 partial sums into FP64 after
+                            each.  0 (default): 512; else a power of two in [128, 2048].  Takes
+                            effect at the next force call; a tuning knob (bh_graph_capture
+                            records the value of the capture). */
 } bh_options;
 
 /* ---- context ---------------------------------------------------------- */

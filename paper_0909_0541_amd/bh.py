@@ -54,7 +54,7 @@ MLP_FEATURES, MLP_HIDDEN, MLP_PARAMS = 12, 64, 5057
 
 class _Options(C.Structure):
     _fields_ = [("waves_per_cu", C.c_int32), ("timing", C.c_int32), ("split_visits", C.c_int32),
-                ("quadrupole", C.c_int32), ("curve", C.c_int32)]
+                ("quadrupole", C.c_int32), ("curve", C.c_int32), ("list_tile", C.c_int32)]
 
 
 def load():
@@ -168,7 +168,7 @@ class Context:
 
     def __init__(self, stream: torch.cuda.Stream | None = None, waves_per_cu: int | None = None,
                  timing: bool = False, split_visits: int | None = None, quadrupole: bool = False,
-                 curve: int = 0):
+                 curve: int = 0, list_tile: int = 0):
         self._L = load()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: libbh runs only on the device")
@@ -187,6 +187,7 @@ class Context:
             opt.split_visits = int(split_visits)
         opt.quadrupole = 1 if quadrupole else 0
         opt.curve = int(curve)
+        opt.list_tile = int(list_tile)
         self._check(self._L.bh_set_options(self._h, C.byref(opt)))
 
     def _check(self, st, h=0):
@@ -208,7 +209,8 @@ class Context:
             pass
 
     def set_options(self, waves_per_cu: int | None = None, timing: bool | None = None,
-                    split_visits: int | None = None, quadrupole: bool | None = None, curve: int | None = None):
+                    split_visits: int | None = None, quadrupole: bool | None = None, curve: int | None = None,
+                    list_tile: int | None = None):
         opt = _Options()
         self._check(self._L.bh_get_options(self._h, C.byref(opt)))
         if waves_per_cu is not None:
@@ -221,6 +223,8 @@ class Context:
             opt.quadrupole = 1 if quadrupole else 0
         if curve is not None:
             opt.curve = int(curve)
+        if list_tile is not None:
+            opt.list_tile = int(list_tile)
         self._check(self._L.bh_set_options(self._h, C.byref(opt)))
 
     def sync(self):

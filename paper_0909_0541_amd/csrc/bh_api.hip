@@ -438,6 +438,9 @@ bh_status bh_set_options(bh_ctx *c, const bh_options *opt) {
     return fail(c, BH_EINVAL, "split_visits must be -1, 0 or >= 64");
   if (opt->quadrupole != 0 && opt->quadrupole != 1) return fail(c, BH_EINVAL, "quadrupole must be 0 or 1");
   if (opt->curve != 0 && opt->curve != 1) return fail(c, BH_EINVAL, "curve must be 0 (Morton) or 1 (Peano-Hilbert)");
+  if (opt->list_tile != 0 && (opt->list_tile < kMinTile || opt->list_tile > kMaxTile ||
+                              (opt->list_tile & (opt->list_tile - 1)) != 0))
+    return fail(c, BH_EINVAL, "list_tile must be 0 or a power of two in [128, 2048]");
   c->opt = *opt;
   return BH_OK;
 }
@@ -534,11 +537,18 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
     c->have_forces = true;
     return BH_OK;
   }
-  // list pools: start from an estimate, grow to what a walk reports it needed
+  // list pools: start from an estimate (32 far and 4 near entries per
+  // particle), grow to what a walk reports it needed; the capacities count
+  // chunks of the current tile (recounted when the tile changes)
+  const int tile = c->opt.list_tile > 0 ? c->opt.list_tile : kDefaultTile;
   if (c->far_cap == 0) {
-    c->far_cap = (int32_t)std::max<int64_t>(4096, c->n / 16);
-    c->near_cap = (int32_t)std::max<int64_t>(4096, c->n / 64);
+    c->far_cap = (int32_t)std::max<int64_t>(4096, 32 * c->n / tile);
+    c->near_cap = (int32_t)std::max<int64_t>(4096, 8 * c->n / tile);
+  } else if (c->pool_tile != tile) {
+    c->far_cap = (int32_t)std::min<int64_t>((int64_t)c->far_cap * c->pool_tile / tile + 64, INT32_MAX / 2);
+    c->near_cap = (int32_t)std::min<int64_t>((int64_t)c->near_cap * c->pool_tile / tile + 64, INT32_MAX / 2);
   }
+  c->pool_tile = tile;
   WalkListArgs W{};
   W.nodes = P<NodeRec>(c->nodes);
   W.sys = P<SysInfo>(c->sys);
@@ -585,15 +595,15 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
   SplitBuffers S{};
   int32_t nsegs_host = 0;
   for (int attempt = 0;; ++attempt) {
-    st = ensure(c, c->far_pool, (size_t)c->far_cap * kFarChunk * sizeof(float4), "far list pool");
+    st = ensure(c, c->far_pool, (size_t)c->far_cap * tile * sizeof(float4), "far list pool");
     if (st) return st;
     st = ensure(c, c->far_next, (size_t)c->far_cap * sizeof(int32_t), "far list links");
     if (st) return st;
     if (quad) {
-      st = ensure(c, c->far_slot, (size_t)c->far_cap * kFarChunk * sizeof(int32_t), "far list node slots");
+      st = ensure(c, c->far_slot, (size_t)c->far_cap * tile * sizeof(int32_t), "far list node slots");
       if (st) return st;
     }
-    st = ensure(c, c->near_pool, (size_t)c->near_cap * 2 * kNearChunk * sizeof(float4), "near list pool");
+    st = ensure(c, c->near_pool, (size_t)c->near_cap * tile * sizeof(float4), "near list pool");
     if (st) return st;
     st = ensure(c, c->near_next, (size_t)c->near_cap * sizeof(int32_t), "near list links");
     if (st) return st;
@@ -619,6 +629,8 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
     W.far_slot = quad ? P<int32_t>(c->far_slot) : nullptr;
     W.far_cap = c->far_cap;
     W.near_cap = c->near_cap;
+    W.far_tile = tile;
+    W.near_tile = tile / 2;
     W.glists = P<int32_t>(c->glists);
     W.ctr = P<SplitCounters>(c->split_ctr);
     W.tasks = P<WalkTask>(c->tasks);
@@ -719,6 +731,8 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
   F.near_next = P<int32_t>(c->near_next);
   F.far_slot = quad ? P<int32_t>(c->far_slot) : nullptr;
   F.qpack = quad ? P<float4>(c->qpack) : nullptr;
+  F.far_tile = tile;
+  F.near_tile = tile / 2;
   F.spos = P<double>(c->spos);
   F.smass = P<double>(c->smass);
   F.perm = P<int32_t>(c->perm);

@@ -75,11 +75,13 @@ struct DevInfo {
   alignas(128) int32_t fq[8 * kLineInts];  // force queue heads, one per XCD: fq[x * kLineInts]
 };
 
-// Interaction lists: chunks of kFarChunk far entries (float4 x - c_g, m) and
-// of kNearChunk near entries (kNearChunk float4 values, then kNearChunk
-// float4 rounding residues), 8 KiB each.
-constexpr int kFarChunk = 512;
-constexpr int kNearChunk = 256;
+// Interaction lists: chunks (tiles) of T far entries (float4 x - c_g, m) and
+// of T/2 near entries (T/2 float4 values, then T/2 float4 rounding
+// residues), 16 T bytes each; T = bh_options.list_tile (a power of two in
+// [kMinTile, kMaxTile], default kDefaultTile).
+constexpr int kDefaultTile = 512;
+constexpr int kMinTile = 128;   // a near tile must hold a batch of 64 entries
+constexpr int kMaxTile = 2048;
 constexpr int kChunkRun = 4;    // chunks a walk wave takes from a pool per atomic
 // Near entries: within kNearFrac times the box half-diagonal of the box.
 constexpr double kNearFrac = 0.1;
@@ -151,7 +153,7 @@ struct bh_ctx {
   int device = 0;
   int num_cu = 0;
   std::string err;
-  bh_options opt{0, 0, 0, 0, 0};
+  bh_options opt{0, 0, 0, 0, 0, 0};
   int walk_bpc = 0, force_bpc = 0, force_bpc_q = 0, probe_bpc = 0, nb_bpc[3] = {0, 0, 0};  // resident blocks per CU of the persistent kernels
 
   // current tree
@@ -206,6 +208,7 @@ struct bh_ctx {
   bh::DevBuf far_pool, near_pool;  // list chunks
   bh::DevBuf far_next, near_next;  // int32 chunk links
   int32_t far_cap = 0, near_cap = 0;  // pool capacities in chunks
+  int32_t pool_tile = 0;              // far entries per chunk the capacities count in
   bh::DevBuf gmass;             // FP64 [G] list mass of the last force call
   bh::DevBuf bbox_part;         // FP64 bbox partials
   bh::DevBuf sys;               // SysInfo [nsys]
@@ -333,6 +336,7 @@ struct WalkListArgs {
   int32_t *far_next;
   int32_t *near_next;
   int far_cap, near_cap;
+  int far_tile, near_tile;   // entries per far / near chunk (powers of two)
   int32_t *glists;
   int32_t *glist;
   double *gmass;
@@ -437,6 +441,7 @@ struct ForceArgs {
   const int32_t *gsegfirst;   // group -> first sorted position
   const int32_t *pbase;       // sorted position -> first partial-sum row
   double *psum;               // [rows][4] ax, ay, az, pot
+  int far_tile, near_tile;    // entries per far / near chunk
   const int32_t *far_slot;    // quadrupole sums: node slot of each far entry (near entries: residue .w)
   const float4 *qpack;        // quadrupole sums: [slots][2] second moments
 };

@@ -325,18 +325,18 @@ __global__ __launch_bounds__(kWave) void k_force_lists(ForceArgs a, const float4
 
     int ch = fh;
     for (int left = fn; left > 0;) {
-      const int n = min(left, kFarChunk);
-      const float4 *base = far_pool + (int64_t)ch * kFarChunk;
-      chunk_sum<false, QUAD>(M, base, base, n, R, part, eps2, QUAD ? far_slot + (int64_t)ch * kFarChunk : nullptr,
+      const int n = min(left, a.far_tile);
+      const float4 *base = far_pool + (int64_t)ch * a.far_tile;
+      chunk_sum<false, QUAD>(M, base, base, n, R, part, eps2, QUAD ? far_slot + (int64_t)ch * a.far_tile : nullptr,
                              qpack);
       left -= n;
       if (left > 0) ch = far_next[ch];
     }
     ch = nh;
     for (int left = nn; left > 0;) {
-      const int n = min(left, kNearChunk);
-      const float4 *base = near_pool + (int64_t)ch * (2 * kNearChunk);
-      chunk_sum<true, QUAD>(M, base, base + kNearChunk, n, R, part, eps2, nullptr, qpack);
+      const int n = min(left, a.near_tile);
+      const float4 *base = near_pool + (int64_t)ch * (2 * a.near_tile);
+      chunk_sum<true, QUAD>(M, base, base + a.near_tile, n, R, part, eps2, nullptr, qpack);
       left -= n;
       if (left > 0) ch = near_next[ch];
     }

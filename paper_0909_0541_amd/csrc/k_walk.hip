@@ -419,22 +419,22 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) v
         if (push) stk[sp + rank_below(pm)] = rng;
         const int nf = __popcll(fm), nn = __popcll(nm);
         if (nf > 0) {
-          fok = reserve(F, nf, kFarChunk, fsrc, &a.info->far_chunks, a.far_cap, a.far_next, lane, fok);
+          fok = reserve(F, nf, a.far_tile, fsrc, &a.info->far_chunks, a.far_cap, a.far_next, lane, fok);
           if (fok && emit && !near) {
             const int pos = F.count + rank_below(fm);
-            const int64_t at = (int64_t)chunk_of(F, pos, kFarChunk) * kFarChunk + pos % kFarChunk;
+            const int64_t at = (int64_t)chunk_of(F, pos, a.far_tile) * a.far_tile + (pos & (a.far_tile - 1));
             a.far_pool[at] = hi4;
             if (a.far_slot) a.far_slot[at] = rcur.child < 0 ? -1 : ncur;
           }
           F.count += nf;
         }
         if (nn > 0) {
-          nok = reserve(N, nn, kNearChunk, nsrc, &a.info->near_chunks, a.near_cap, a.near_next, lane, nok);
+          nok = reserve(N, nn, a.near_tile, nsrc, &a.info->near_chunks, a.near_cap, a.near_next, lane, nok);
           if (nok && emit && near) {
             const int pos = N.count + rank_below(nm);
-            float4 *base = a.near_pool + (int64_t)chunk_of(N, pos, kNearChunk) * (2 * kNearChunk);
-            base[pos % kNearChunk] = hi4;
-            base[kNearChunk + pos % kNearChunk] = lo4;
+            float4 *base = a.near_pool + (int64_t)chunk_of(N, pos, a.near_tile) * (2 * a.near_tile);
+            base[pos & (a.near_tile - 1)] = hi4;
+            base[a.near_tile + (pos & (a.near_tile - 1))] = lo4;
           }
           N.count += nn;
         }
