@@ -45,6 +45,9 @@ if ROOT not in sys.path:
 METRIC = "tree-force interactions/s and particles/s at 1e-3 RMS force error, learned vs fixed θ"
 FP32_VALU_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
 FLOPS_PER_INTERACTION = 20      # 3 sub, 3 FMA (r^2), rsqrt, 3 mul, 3 FMA (acc), 1 add (pot)
+HBM_PEAK_GBPS = 8000.0          # MI355X published HBM3E bandwidth
+NODE_BYTES = 56                 # node record bytes a walk visit reads (centre of mass, mass, side, offset, children)
+FAR_BYTES, NEAR_BYTES = 16, 32  # list bytes written per far / near entry
 HELDOUT_SEED = 54321            # a second judge sample, not used by any calibration
 
 
@@ -52,7 +55,13 @@ HELDOUT_SEED = 54321            # a second judge sample, not used by any calibra
 # of this script (bytes per launch, scaled by the counters' reading of a
 # device copy of known size), valid only for the kernel source and theta it
 # was taken on.
-TRAFFIC = {}
+TRAFFIC = {
+    # clustered box, 4,194,304 particles, theta 0.3328125 (the 1e-3 RMS theta):
+    # FETCH_SIZE 5477823.9 KiB x 1.99987 (a 512 MiB device copy reads as
+    # 262161.44 KiB) + WRITE_SIZE 284456.5 KiB x 1.0 (the copy writes 524288 KiB)
+    "clustered_4m": {"theta": 0.3328125, "bytes_per_launch": 11509120575,
+                     "k_force_sha256": "a290be4fe208ca907b3c8d22de5c2ee2af8c692b6eb2d569808aa69ac0c4f415"},
+}
 
 
 def traffic_for(workload, theta):
@@ -437,10 +446,19 @@ def equal_error(args, w, dpos, dmass, net, headline: bool):
         theta = w.theta if args.theta is None else args.theta
     ms_eager, st = learned.timed_steps(fixed, args.steps, args.warmup, theta=theta)
     inter = st.interactions
+    t_walk = _stages(st)["walk"]
+    walk_bytes = (NODE_BYTES * st.node_visits + FAR_BYTES * (st.list_entries - st.near_entries)
+                  + NEAR_BYTES * st.near_entries)
+    walk = {"bound": "latency", "achieved": walk_bytes / (t_walk * 1e-3) / 1e9, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "node_visits": st.node_visits, "list_entries": st.list_entries, "near_entries": st.near_entries,
+            "bytes_per_step": walk_bytes,
+            "note": "algorithmic bytes (56 B per node visit read, 16/32 B per far/near list entry written) over "
+                    "the walk kernel's time; the node reads mostly hit the XCD's L2, so HBM is not its bound"}
+    walk["frac"] = walk["achieved"] / HBM_PEAK_GBPS
     rep = {"n": n, "theta": theta, "rms_force_error": judge.rms(fixed.acc),
            "heldout_rms_force_error": heldout.rms(fixed.acc), "interactions_per_step": inter,
            "stage_ms": _stages(st), "eager_ms_per_step": ms_eager, "groups": st.n_groups, "cells": st.n_cells,
-           "max_list": st.max_list}
+           "max_list": st.max_list, "walk_roofline": walk}
     off = np.array([0, n], dtype=np.int64)
     gf = bh.Context(waves_per_cu=args.waves_per_cu, curve=args.curve)
     gf.graph_capture(off, dpos, dmass, w.n_crit, [w.eps], [theta])
@@ -593,6 +611,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": traffic_for(w.name, theta),
                      "kernel": "k_force_lists", "flops_per_interaction": FLOPS_PER_INTERACTION},
+        "walk_roofline": rep["walk_roofline"],
         "force_kernel_interactions_per_s": inter / (t_force * 1e-3),
         "walk_plus_force_interactions_per_s": inter / ((rep["stage_ms"]["walk"] + t_force) * 1e-3),
     }

@@ -99,6 +99,8 @@ typedef struct {
   int32_t n_theta_calls;
   int32_t n_theta_fallback; /* last force call: groups whose per-group theta was NaN (walked with the
                                call's theta) */
+  int64_t node_visits;      /* last force call: nodes the group walk tested */
+  int64_t near_entries;     /* last force call: list entries written to near lists (the rest are far) */
 } bh_stats;
 
 typedef struct {
@@ -133,7 +135,7 @@ typedef struct {
   int32_t list_tile;     /* entries per chunk of a group's far interaction list (its near list uses
                             chunks of half as many): the walk hands lists to the force sum in these
                             tiles, and the force sum folds its FP32 partial sums into FP64 after
-                            each.  0 (default): 512; else a power of two in [128, 2048].  Takes
+                            each.  0 (default): 1024; else a power of two in [128, 2048].  Takes
                             effect at the next force call; a tuning knob (bh_graph_capture
                             records the value of the capture). */
 } bh_options;

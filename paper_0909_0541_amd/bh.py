@@ -42,7 +42,7 @@ class _Stats(C.Structure):
                 ("n_walk_attempts", C.c_int32), ("t_particle_ms", C.c_double), ("n_particle_calls", C.c_int32),
                 ("n_neighbor_calls", C.c_int32), ("t_neighbor_ms", C.c_double), ("neighbor_pairs", C.c_int64),
                 ("neighbor_tests", C.c_int64), ("t_theta_ms", C.c_double), ("n_theta_calls", C.c_int32),
-                ("n_theta_fallback", C.c_int32)]
+                ("n_theta_fallback", C.c_int32), ("node_visits", C.c_int64), ("near_entries", C.c_int64)]
 
 
 class _Mlp(C.Structure):
@@ -161,6 +161,8 @@ class Stats:
     t_theta_ms: float
     n_theta_calls: int
     n_theta_fallback: int
+    node_visits: int
+    near_entries: int
 
 
 class Context:

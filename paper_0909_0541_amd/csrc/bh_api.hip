@@ -965,6 +965,8 @@ bh_status bh_get_stats(bh_ctx *c, bh_stats *out) {
     out->n_split_levels = c->last_depth;
     out->n_walk_attempts = c->last_attempts;
     out->n_theta_fallback = d.theta_fallback;
+    out->node_visits = (int64_t)d.node_visits;
+    out->near_entries = (int64_t)d.near_entries;
   }
   out->t_build_ms = timer_take(c->t_build, &out->n_build_calls);
   out->t_groups_ms = timer_take(c->t_groups, &out->n_groups_calls);

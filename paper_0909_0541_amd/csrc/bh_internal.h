@@ -66,6 +66,8 @@ struct DevInfo {
   unsigned long long nb_tests;  // neighbour search: candidate pairs whose distance was tested
   int32_t theta_fallback;  // groups of the last walk whose per-group theta was NaN (walked with the call's theta)
   int32_t pad0;
+  unsigned long long node_visits;   // nodes the last walk tested (all its units)
+  unsigned long long near_entries;  // list entries the last walk wrote to near lists
   // Counters that every wave of a kernel updates, each in a 128-byte line of
   // its own (atomics on one line serialise behind each other).
   alignas(128) int32_t queue2;  // force work queue head
@@ -79,7 +81,7 @@ struct DevInfo {
 // of T/2 near entries (T/2 float4 values, then T/2 float4 rounding
 // residues), 16 T bytes each; T = bh_options.list_tile (a power of two in
 // [kMinTile, kMaxTile], default kDefaultTile).
-constexpr int kDefaultTile = 512;
+constexpr int kDefaultTile = 1024;
 constexpr int kMinTile = 128;   // a near tile must hold a batch of 64 entries
 constexpr int kMaxTile = 2048;
 constexpr int kChunkRun = 4;    // chunks a walk wave takes from a pool per atomic

@@ -112,6 +112,8 @@ __global__ void k_reset_force_counters(DevInfo *info) {
     info->list_entries = 0;
     info->max_list = 0;
     info->theta_fallback = 0;
+    info->node_visits = 0;
+    info->near_entries = 0;
     info->err &= ~kErrPool;
     for (int x = 0; x < 8; ++x) {
       info->xq[x * kLineInts] = 0;

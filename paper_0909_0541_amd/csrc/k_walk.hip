@@ -529,6 +529,10 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) v
         }
       }
     }
+    if (lane == 0) {
+      atomicAdd(&a.info->node_visits, (unsigned long long)visits);
+      atomicAdd(&a.info->near_entries, (unsigned long long)N.count);
+    }
     if (!corrupt) {
 #pragma unroll
       for (int d = 1; d < kWave; d <<= 1) lmass += shfl_xor_d(lmass, d);
