@@ -110,7 +110,9 @@ typedef struct {
                             stack to up to 16 new walk tasks, which waves with no group left
                             take in the same launch, so that long lists are walked and summed
                             by several waves; tasks 5 hand-overs deep walk to the end (0:
-                            default, automatic: 48 per particle of a walk wave, i.e.
+                            default, automatic: a single system is not split (its walk then
+                            runs without the split machinery, which is faster); a batch
+                            splits at 48 per particle of a walk wave, i.e.
                             48 n / (CUs x walk waves per CU), at least 12288, and at least 4
                             times the mean list length of the previous force call on the
                             context, so that only outlier walks split; -1: never; else

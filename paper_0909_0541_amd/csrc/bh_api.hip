@@ -575,11 +575,15 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
   // kSplitMeanFactor times the mean list length of the previous walk on this
   // context, so that where every list is long (small theta) only the outliers
   // split: splitting most groups costs more than it balances.
+  // A single system is not split by default: its lists are rarely far longer
+  // than the mean, and the walk without the split machinery is faster (see
+  // k_walk_lists).
   const int64_t auto_cap = std::max<int64_t>(kSplitVisits, kSplitPerParticle * c->n / std::max(grid, 1));
   const bool auto_split = c->opt.split_visits == 0;
   const int visit_cap = c->opt.split_visits < 0
                             ? 0
-                            : (auto_split ? (int)std::min<int64_t>(auto_cap, INT32_MAX / 2) : c->opt.split_visits);
+                            : (auto_split ? (c->nsys > 1 ? (int)std::min<int64_t>(auto_cap, INT32_MAX / 2) : 0)
+                                          : c->opt.split_visits);
   if (!c->walk_hist.p) {
     st = ensure(c, c->walk_hist, 4 * sizeof(int32_t), "walk history");
     if (st) return st;

@@ -153,13 +153,14 @@ __device__ __forceinline__ int wait_slot(const WalkListArgs &a, int t, int lane)
 // the XCDs round robin), so that the waves sharing an L2 walk neighbouring
 // groups and read mostly the same nodes; a wave whose eighth is done takes
 // from the others.
+template <bool SPLIT>
 __device__ __forceinline__ int next_unit(const WalkListArgs &a, int G, int xcd, int &tried, int &ticket, bool &waiter,
                                          int &task, int lane) {
   task = -1;
   int g = -1;
   for (;;) {
     int rc = -1;
-    if (a.visit_cap > 0) {
+    if (SPLIT && a.visit_cap > 0) {
       if (ticket < 0 && tried >= 8) {
         const int head = __builtin_amdgcn_readfirstlane(
             __hip_atomic_load(&a.ctr->queue, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
@@ -182,7 +183,7 @@ __device__ __forceinline__ int next_unit(const WalkListArgs &a, int G, int xcd, 
         }
         ++tried;
       }
-      if (g >= 0 || a.visit_cap <= 0) break;
+      if (g >= 0 || !SPLIT || a.visit_cap <= 0) break;
       if (ticket < 0) {
         // a bounded number of waves wait for tasks; the others leave (a
         // wave that holds no ticket owes no slot), which keeps the polling
@@ -230,7 +231,11 @@ __device__ __forceinline__ int key_depth(int key) {
 // segment).
 // Four waves per SIMD (128 VGPRs, a few spilled) hide more of the node
 // reads' latency than the three that 137 VGPRs allow: measured 5 % (2M
-// particles) to 10 % (8M) shorter walks.
+// particles) to 10 % (8M) shorter walks.  SPLIT = false compiles the walk
+// without split walks (no tasks, no hand-over): it holds far fewer registers
+// (29 instead of 77 scalar registers spilled to vector lanes, none to
+// memory) and walks 5 % faster.
+template <bool SPLIT>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_walk_lists(WalkListArgs a) {
   __shared__ int2 stk[kStack];
   __shared__ int mark[kWave];
@@ -238,8 +243,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) v
   const int G = a.info->n_groups;
   const int nslots = a.nsys + a.info->n_slots;
   // the automatic cap also stays above a multiple of the last mean list
-  int visit_cap = a.visit_cap;
-  if (visit_cap > 0 && a.mean_list)
+  int visit_cap = SPLIT ? a.visit_cap : 0;
+  if (SPLIT && visit_cap > 0 && a.mean_list)
     visit_cap = max(visit_cap, kSplitMeanFactor * min(__builtin_amdgcn_readfirstlane(a.mean_list[0]), INT32_MAX / 64));
 
   const int xcd = blockIdx.x & 7;
@@ -248,7 +253,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) v
   ChunkSource fsrc, nsrc;  // this wave's far and near list chunks
   for (;;) {
     int task;
-    const int g = next_unit(a, G, xcd, tried, ticket, waiter, task, lane);
+    const int g = next_unit<SPLIT>(a, G, xcd, tried, ticket, waiter, task, lane);
     if (g < 0) break;
     const bool is_task = task >= 0;
 
@@ -305,7 +310,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) v
       }
     }
     // units at the deepest level walk to the end
-    int cap = (visit_cap > 0 && key_depth(key) < kSplitDepth) ? visit_cap : 0;
+    int cap = (SPLIT && visit_cap > 0 && key_depth(key) < kSplitDepth) ? visit_cap : 0;
     wave_sync();
     int visits = 0;
     // Software pipeline: the records of the next batch are loaded while the
@@ -449,7 +454,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) v
       if (bcur == 0 && sp == 0) break;
       // Visit cap reached: hand the rest (the popped batch as runs of
       // consecutive nodes, then the stack) to new tasks.
-      if (cap > 0 && visits >= cap) {
+      if (SPLIT && cap > 0 && visits >= cap) {
         if (bcur > 0) {
           const int prev = __shfl_up(ncur, 1, kWave);
           const bool head = lane < bcur && (lane == 0 || ncur != prev + 1);
@@ -597,7 +602,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) v
     }
     // this unit is done; a unit that published tasks orders them before
     // its decrement (the others published nothing that waiters read)
-    if (a.visit_cap > 0) {
+    if (SPLIT && a.visit_cap > 0) {
       if (handed) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       atomicAdd(&a.ctr->pending, lane == 0 ? -1 : 0);
     }
@@ -799,12 +804,15 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7, 7))) v
 
 int walk_lists_blocks_per_cu() {
   int b = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_walk_lists, kWave, 0) != hipSuccess || b < 1) b = 8;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_walk_lists<true>, kWave, 0) != hipSuccess || b < 1) b = 8;
   return b;
 }
 
 void walk_lists_device(const WalkListArgs &a, int grid, hipStream_t s) {
-  k_walk_lists<<<(unsigned)grid, kWave, 0, s>>>(a);
+  if (a.visit_cap > 0)
+    k_walk_lists<true><<<(unsigned)grid, kWave, 0, s>>>(a);
+  else
+    k_walk_lists<false><<<(unsigned)grid, kWave, 0, s>>>(a);
 }
 
 void split_reset(SplitCounters *ctr, const DevInfo *info, WalkTask *tasks, int task_cap, hipStream_t s) {
