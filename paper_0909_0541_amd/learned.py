@@ -64,12 +64,12 @@ def _dev(a, dtype=torch.float32):
 WALK_WEIGHT = 2.0  # walk time per list entry / force time per entry and lane pass (measured)
 
 
-def group_passes(c: int) -> float:
+def group_passes(c: int, walk_weight: float = WALK_WEIGHT) -> float:
     """Time of a group per list entry, in force-kernel lane passes: the walk
-    (WALK_WEIGHT) plus one pass per member block of at most 64, divided by
+    (walk_weight) plus one pass per member block of at most 64, divided by
     the lane partitions a small block uses (as the force kernel splits them)."""
     nb = (c + 63) // 64
-    total = WALK_WEIGHT
+    total = walk_weight
     for b in range(nb):
         m = c * (b + 1) // nb - c * b // nb
         R = 1
@@ -80,7 +80,7 @@ def group_passes(c: int) -> float:
 
 
 def group_tables(ctx: bh.Context, dpos, dmass, eps: float, n_crit: int, n_sample: int, seed: int,
-                 ladder=LADDER):
+                 ladder=LADDER, walk_weight: float = WALK_WEIGHT):
     """Features, costs and errors of a seeded sample of groups over a theta ladder.
 
     Returns dict: feat [S,12], count [S], cost [S,K], err [S,K] (sum of squared
@@ -103,7 +103,7 @@ def group_tables(ctx: bh.Context, dpos, dmass, eps: float, n_crit: int, n_sample
     a_dir = a_dir.cpu().numpy()
     nd = np.linalg.norm(a_dir, axis=1)
     nd = np.where(nd > 0, nd, np.inf)
-    passes = np.array([group_passes(int(c)) for c in count])
+    passes = np.array([group_passes(int(c), walk_weight) for c in count])
     K = len(ladder)
     cost = np.zeros((S, K))
     err = np.zeros((S, K))

@@ -42,6 +42,10 @@ def main(argv=None):
     ap.add_argument("--eval", default="clustered_2m,clustered_4m")
     ap.add_argument("--judge-sample", type=int, default=4096)
     ap.add_argument("--save-tables", default=None, help="write the label tables to this .npz")
+    ap.add_argument("--walk-weight", type=float, default=learned.WALK_WEIGHT,
+                    help="walk time per list entry in force-sum lane passes (the label cost model)")
+    ap.add_argument("--baseline-net", default=None,
+                    help="also evaluate this network on the same workloads, for comparison")
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
     ctx = bh.Context()
@@ -51,7 +55,8 @@ def main(argv=None):
         n, halos, seed = (int(v) for v in spec.split(":"))
         pos, mass, _ = inputs.clustered(n, seed, n_halos=halos)
         dpos, dmass = learned._dev(pos, torch.float64), learned._dev(mass, torch.float64)
-        tb = learned.group_tables(ctx, dpos, dmass, args.eps, args.n_crit, args.groups_per_snapshot, seed)
+        tb = learned.group_tables(ctx, dpos, dmass, args.eps, args.n_crit, args.groups_per_snapshot, seed,
+                                  walk_weight=args.walk_weight)
         tables.append(tb)
         log(json.dumps({"stage": "labels", "snapshot": spec, "groups": int(len(tb["count"])),
                         "seconds": round(time.time() - t0, 1)}))
@@ -89,6 +94,10 @@ def main(argv=None):
         res = learned.equal_error(ctx, dpos, dmass, w.eps, w.n_crit, net, args.target_rms, judge)
         summary[name] = res
         log(json.dumps({"stage": "eval", "workload": name, **res}))
+        if args.baseline_net:
+            base = learned.ThetaNet.load(args.baseline_net)
+            rb = learned.equal_error(ctx, dpos, dmass, w.eps, w.n_crit, base, args.target_rms, judge)
+            log(json.dumps({"stage": "eval_baseline", "workload": name, **rb}))
         del dpos, dmass
     return summary
 
