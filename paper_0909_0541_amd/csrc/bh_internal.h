@@ -262,10 +262,12 @@ void scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *tot
                         hipStream_t s);
 
 // sort.hip: stable LSD radix sort of (u64 key, u32 value) pairs on bits
-// [bit0, bit1); ping-pong buffers; returns the index (0/1) holding the result.
+// [bit0, bit1) (at most 64 bits); ping-pong buffers; returns the index (0/1)
+// holding the result.  hist holds radix_hist_bytes(n); a look-back timeout
+// sets kErrWait in *err (when err is not null).
 size_t radix_hist_bytes(int64_t n);
 int radix_sort_pairs(uint64_t *k0, uint64_t *k1, uint32_t *v0, uint32_t *v1, int64_t n, int bit0,
-                     int bit1, uint32_t *hist, void *scan_tmp, hipStream_t s);
+                     int bit1, uint32_t *hist, void *scan_tmp, int32_t *err, hipStream_t s);
 // one stable pass on an external 8-bit digit: digit(i) = sys_in[v[i]] >> shift & 255
 int radix_pass_by_system(uint64_t *k0, uint64_t *k1, uint32_t *v0, uint32_t *v1, int cur, int64_t n,
                          const int32_t *sys_in, int shift, uint32_t *hist, void *scan_tmp, hipStream_t s);

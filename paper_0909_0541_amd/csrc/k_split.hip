@@ -153,7 +153,8 @@ void split_finish_device(SplitBuffers &S, const int32_t *ginfo, int32_t *glist, 
                                                                                               rank);
     k_seg_place<<<blocks(cap), 256, 0, s>>>(rank, S.ctr, cap, order);
   } else {
-    const int cur = radix_sort_pairs(S.keys[0], S.keys[1], S.vals[0], S.vals[1], cap, 0, 64, S.hist, S.scan_tmp, s);
+    const int cur = radix_sort_pairs(S.keys[0], S.keys[1], S.vals[0], S.vals[1], cap, 0, 64, S.hist, S.scan_tmp,
+                                     &info->err, s);
     order = S.vals[cur];
   }
   S.order = order;

@@ -599,7 +599,8 @@ void build_tree_device(TreeBuffers &B, hipStream_t s) {
   if (nsys > 1) k_system_of_input<<<blocks_for(n), 256, 0, s>>>(B.sys, nsys, n, B.sys_in);
   k_keys<<<blocks_for(n), 256, 0, s>>>(B.pos, B.mass, n, nsys > 1 ? B.sys_in : nullptr, B.sys, B.curve, B.keys[0],
                                         B.vals[0], B.info);
-  int cur = radix_sort_pairs(B.keys[0], B.keys[1], B.vals[0], B.vals[1], n, 0, 64, B.hist, B.scan_tmp, s);
+  int cur = radix_sort_pairs(B.keys[0], B.keys[1], B.vals[0], B.vals[1], n, 0, 64, B.hist, B.scan_tmp,
+                             &B.info->err, s);
   if (nsys > 1) {
     for (int shift = 0; (nsys - 1) >> shift; shift += 8)
       cur = radix_pass_by_system(B.keys[0], B.keys[1], B.vals[0], B.vals[1], cur, n, B.sys_in, shift, B.hist,
