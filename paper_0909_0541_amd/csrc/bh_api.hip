@@ -1090,26 +1090,17 @@ static bh_status features_common(bh_ctx *c, const double *eps_sys, float *feat) 
   st = upload(c, c->feps.p, c->feps_host.data(), sizeof(double) * (size_t)c->nsys);
   if (st) return st;
   if (c->n == 0) return BH_OK;
-  FeatureArgs a{};
-  a.ginfo = P<int32_t>(c->ginfo);
-  a.gbox = P<double>(c->gbox);
-  a.spos = P<double>(c->spos);
-  a.smass = P<double>(c->smass);
-  a.pparent = P<int32_t>(c->pparent);
-  a.cparent = P<int32_t>(c->cparent);
-  a.ccount = P<int32_t>(c->ccount);
-  a.cslot = P<int32_t>(c->cslot);
-  a.level = P<int8_t>(c->level);
-  a.nodes = P<NodeRec>(c->nodes);
-  a.eps = P<double>(c->feps);
-  a.info = P<DevInfo>(c->info);
-  a.feat = feat;
-  group_features_device(a, c->n, c->num_cu, c->stream);
   ProbeArgs pa{};
   pa.nodes = P<NodeRec>(c->nodes);
   pa.ginfo = P<int32_t>(c->ginfo);
   pa.gbox = P<double>(c->gbox);
+  pa.spos = P<double>(c->spos);
   pa.smass = P<double>(c->smass);
+  pa.pparent = P<int32_t>(c->pparent);
+  pa.cparent = P<int32_t>(c->cparent);
+  pa.ccount = P<int32_t>(c->ccount);
+  pa.cslot = P<int32_t>(c->cslot);
+  pa.level = P<int8_t>(c->level);
   pa.eps = P<double>(c->feps);
   pa.info = P<DevInfo>(c->info);
   pa.nsys = c->nsys;

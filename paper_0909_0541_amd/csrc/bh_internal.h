@@ -408,7 +408,9 @@ struct ProbeArgs {
   const NodeRec *nodes;
   const int32_t *ginfo;
   const double *gbox;
-  const double *smass;
+  const double *spos, *smass;
+  const int32_t *pparent, *cparent, *ccount, *cslot;
+  const int8_t *level;
   const double *eps;  // per system
   DevInfo *info;      // queue must be reset before the launch
   int nsys;
@@ -477,21 +479,9 @@ void reset_info_device(DevInfo *info, hipStream_t s);
 // k_mlp.hip: per-group theta from a 12 -> 64 -> 64 -> 1 network
 constexpr int kMlpParams = 64 * 12 + 64 + 64 * 64 + 64 + 64 + 1;
 constexpr float kThetaMin = 0.3f, kThetaSpan = 0.7f;
-struct FeatureArgs {
-  const int32_t *ginfo;
-  const double *gbox;
-  const double *spos, *smass;
-  const int32_t *pparent, *cparent, *ccount, *cslot;
-  const int8_t *level;
-  const NodeRec *nodes;
-  const double *eps;  // per system
-  DevInfo *info;
-  float *feat;        // [G][12]
-};
 struct MlpWork {  // per-sample activations and gradients of a training batch
   float *xn, *h1, *h2, *dz1, *dz2, *dy, *loss, *wsum;
 };
-void group_features_device(const FeatureArgs &a, int64_t cap, int num_cu, hipStream_t s);
 void mlp_infer_device(const float *params, const float *mu, const float *sigma, const float *x, int64_t rows,
                       int64_t cap_rows, const DevInfo *info, float shift, float *theta, hipStream_t s);
 void mlp_grad_device(const float *params, const float *mu, const float *sigma, int B, const float *x,

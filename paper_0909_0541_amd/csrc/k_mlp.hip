@@ -11,7 +11,8 @@
 //   f3 = log2(l(A1) / (R + eps)), f4 = log2(m(A1) / m_g),
 //   f5 = |com(A1) - c_g| / l(A1), f11 = log2(m(A2) / m_g),
 // and, from the group's interaction list at theta = 1 (the probe walk) with
-// d = com - c_g over the entries outside the box:
+// d = com - c_g over the entries outside the box (the probe walk, one wave per
+// group, computes all twelve):
 //   f6 = log2(|sum m d / (d^2 + eps^2)^1.5| + 2^-100),
 //   f7 = log2(sum m / (d^2 + eps^2) + 2^-100),
 //   f8 = log2(1 + single particles outside the box), f9 = log2(list length),
@@ -36,80 +37,6 @@ constexpr int kIn = 12, kHid = 64;
 constexpr int oW1 = 0, oB1 = oW1 + kHid * kIn, oW2 = oB1 + kHid, oB2 = oW2 + kHid * kHid, oW3 = oB2 + kHid,
               oB3 = oW3 + kHid;
 static_assert(oB3 + 1 == kMlpParams, "parameter layout");
-
-// ---- features --------------------------------------------------------------
-
-__device__ __forceinline__ double norm3(double a, double b, double c) {
-  return sqrt(__dadd_rn(__dadd_rn(__dmul_rn(a, a), __dmul_rn(b, b)), __dmul_rn(c, c)));
-}
-
-// One wave per group (grid-stride): lanes sum the members' mass moments, lane
-// 0 finishes the features.
-__global__ __launch_bounds__(kWave) void k_group_features(FeatureArgs a) {
-  const int lane = lane_id();
-  const int64_t G = a.info->n_groups;
-  for (int64_t g = blockIdx.x; g < G; g += gridDim.x) {
-    const int f = a.ginfo[3 * g], c = a.ginfo[3 * g + 1], s = a.ginfo[3 * g + 2];
-    double mg = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
-    for (int i = f + lane; i < f + c; i += kWave) {
-      const double m = a.smass[i];
-      const double *x = a.spos + 3 * (int64_t)i;
-      mg = __dadd_rn(mg, m);
-      mx = __dadd_rn(mx, __dmul_rn(m, x[0]));
-      my = __dadd_rn(my, __dmul_rn(m, x[1]));
-      mz = __dadd_rn(mz, __dmul_rn(m, x[2]));
-    }
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-      mg += shfl_xor_d(mg, d);
-      mx += shfl_xor_d(mx, d);
-      my += shfl_xor_d(my, d);
-      mz += shfl_xor_d(mz, d);
-    }
-    if (lane != 0) continue;
-    const double eps = a.eps[s];
-    double cen[3], e[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const double lo = a.gbox[6 * g + k], hi = a.gbox[6 * g + 3 + k];
-      cen[k] = __dmul_rn(__dadd_rn(lo, hi), 0.5);
-      e[k] = __dsub_rn(hi, lo);
-    }
-    const double R = norm3(e[0], e[1], e[2]) / 2.0;
-    const double re = __dadd_rn(R, eps);
-    float out[kIn];
-#pragma unroll
-    for (int k = 0; k < kIn; ++k) out[k] = 0.0f;
-    out[0] = (float)log2((double)c);
-    out[1] = (float)log2(__dadd_rn(1.0, R / eps));
-    out[2] = (float)(norm3(__dsub_rn(mx / mg, cen[0]), __dsub_rn(my / mg, cen[1]), __dsub_rn(mz / mg, cen[2])) / re);
-    // A1: the smallest split cell (not a bucket) holding more than c particles;
-    // the cells of this tree are split cells (single-child chains are not kept)
-    int p = a.pparent[f];
-    for (int it = 0; p >= 0 && (a.level[p] == kKeyLevels || a.ccount[p] <= c); ++it) {
-      if (it > 2 * kKeyLevels + 2) {
-        atomicOr(&a.info->err, kErrBuild);
-        p = -1;
-        break;
-      }
-      p = a.cparent[p];
-    }
-    if (p >= 0) {
-      const int q = a.cparent[p];
-      const NodeRec r1 = a.nodes[a.cslot[p]];
-      const NodeRec r2 = a.nodes[a.cslot[q >= 0 ? q : p]];
-      out[3] = (float)log2(r1.l / re);
-      out[4] = (float)log2(r1.m / mg);
-      out[5] = (float)(norm3(__dsub_rn(r1.com[0], cen[0]), __dsub_rn(r1.com[1], cen[1]),
-                             __dsub_rn(r1.com[2], cen[2])) / r1.l);
-      out[11] = (float)log2(r2.m / mg);
-    }
-    // f6..f10 come from the probe walk (k_probe), which runs after this kernel
-#pragma unroll
-    for (int k = 0; k < kIn; ++k)
-      if (k < 6 || k == 11) a.feat[g * kIn + k] = out[k];
-  }
-}
 
 // ---- inference (bfloat16 matrix cores) --------------------------------------
 
@@ -310,9 +237,6 @@ __global__ void k_adam(float *__restrict__ P, const float *__restrict__ g, float
 
 }  // namespace
 
-void group_features_device(const FeatureArgs &a, int64_t cap, int num_cu, hipStream_t s) {
-  if (cap > 0) k_group_features<<<(unsigned)std::min<int64_t>(cap, (int64_t)num_cu * 16), kWave, 0, s>>>(a);
-}
 
 void mlp_infer_device(const float *params, const float *mu, const float *sigma, const float *x, int64_t rows,
                       int64_t cap_rows, const DevInfo *info, float shift, float *theta, hipStream_t s) {

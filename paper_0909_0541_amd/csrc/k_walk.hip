@@ -44,6 +44,10 @@ constexpr int kTaskStack = 512;   // largest first stack of a task
 constexpr int kWaiters = 64;      // waves that wait for tasks once the groups are taken
 constexpr int kProbeStack = 512;  // range stack of the probe walk (its theta = 1 lists are short)
 
+__device__ __forceinline__ double norm3(double a, double b, double c) {
+  return sqrt(__dadd_rn(__dadd_rn(__dmul_rn(a, a), __dmul_rn(b, b)), __dmul_rn(c, c)));
+}
+
 // The block is one wavefront: a barrier orders its LDS writes and reads.
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }
 
@@ -637,7 +641,9 @@ __global__ void k_reset_queue(DevInfo *info) {
 // R is taken whole (as a monopole) without the opening test.  Sums: the field
 // and its scale at the box centre from the entries whose centre of mass lies
 // outside the box, the count of single particles among them, the number of
-// entries and the mass inside the box.  Writes features f6..f10.
+// entries and the mass inside the box.  Writes features f6..f10, and the
+// group's own features f0..f5 and f11 (members' mass and centre of mass, the
+// smallest split cell holding more than the group and the one above it).
 // Seven waves per SIMD (at most 72 VGPRs, no spills) hide more of the node
 // reads' latency than the five the compiler would choose: measured 22 % (2M)
 // and 31 % (4M) shorter feature stages.
@@ -775,8 +781,16 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7, 7))) v
       if (lane == 0) atomicOr(&a.info->err, kErrStack);
       continue;
     }
-    double mg = 0.0;
-    for (int i = gf + lane; i < gf + gc; i += kWave) mg = __dadd_rn(mg, a.smass[i]);
+    // the members' mass and mass moments
+    double mg = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
+    for (int i = gf + lane; i < gf + gc; i += kWave) {
+      const double m = a.smass[i];
+      const double *x = a.spos + 3 * (int64_t)i;
+      mg = __dadd_rn(mg, m);
+      mx = __dadd_rn(mx, __dmul_rn(m, x[0]));
+      my = __dadd_rn(my, __dmul_rn(m, x[1]));
+      mz = __dadd_rn(mz, __dmul_rn(m, x[2]));
+    }
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
       ax += shfl_xor_d(ax, d);
@@ -785,17 +799,52 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7, 7))) v
       S += shfl_xor_d(S, d);
       m_in += shfl_xor_d(m_in, d);
       mg += shfl_xor_d(mg, d);
+      mx += shfl_xor_d(mx, d);
+      my += shfl_xor_d(my, d);
+      mz += shfl_xor_d(mz, d);
       n_part += __shfl_xor(n_part, d, kWave);
     }
     if (lane == 0) {
       const double tiny = 0x1p-100;
       float *f = a.feat + 12 * (int64_t)g;
-      f[6] = (float)log2(__dadd_rn(sqrt(__dadd_rn(__dadd_rn(__dmul_rn(ax, ax), __dmul_rn(ay, ay)), __dmul_rn(az, az))),
-                                   tiny));
+      f[6] = (float)log2(__dadd_rn(norm3(ax, ay, az), tiny));
       f[7] = (float)log2(__dadd_rn(S, tiny));
       f[8] = (float)log2(1.0 + (double)n_part);
       f[9] = (float)log2((double)nlist);
       f[10] = (float)log2(m_in / mg);
+      // the group's own features
+      const double R = sqrt(hd2) / 2.0;
+      const double re = __dadd_rn(R, eps);
+      f[0] = (float)log2((double)gc);
+      f[1] = (float)log2(__dadd_rn(1.0, R / eps));
+      f[2] = (float)(norm3(__dsub_rn(mx / mg, cen[0]), __dsub_rn(my / mg, cen[1]), __dsub_rn(mz / mg, cen[2])) / re);
+      // A1: the smallest split cell (not a bucket) holding more than c
+      // particles (the cells of this tree are split cells: single-child
+      // chains are not kept), A2 the next one above it
+      float f3 = 0.0f, f4 = 0.0f, f5 = 0.0f, f11 = 0.0f;
+      int p = a.pparent[gf];
+      for (int it = 0; p >= 0 && (a.level[p] == kKeyLevels || a.ccount[p] <= gc); ++it) {
+        if (it > 2 * kKeyLevels + 2) {
+          atomicOr(&a.info->err, kErrBuild);
+          p = -1;
+          break;
+        }
+        p = a.cparent[p];
+      }
+      if (p >= 0) {
+        const int q = a.cparent[p];
+        const NodeRec r1 = a.nodes[a.cslot[p]];
+        const NodeRec r2 = a.nodes[a.cslot[q >= 0 ? q : p]];
+        f3 = (float)log2(r1.l / re);
+        f4 = (float)log2(r1.m / mg);
+        f5 = (float)(norm3(__dsub_rn(r1.com[0], cen[0]), __dsub_rn(r1.com[1], cen[1]), __dsub_rn(r1.com[2], cen[2])) /
+                     r1.l);
+        f11 = (float)log2(r2.m / mg);
+      }
+      f[3] = f3;
+      f[4] = f4;
+      f[5] = f5;
+      f[11] = f11;
     }
   }
 }
