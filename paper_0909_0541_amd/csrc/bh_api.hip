@@ -497,6 +497,7 @@ bh_status bh_make_groups(bh_ctx *c, int32_t n_crit, int64_t *n_groups_out) {
   B.scan_tmp = c->scan_tmp.p;
   B.num_cu = c->num_cu;
   make_groups_device(B, c->stream);
+  c->xq_clean = true;
   st = timer_stop(c, c->t_groups);
   if (st) return st;
   st = hip_check(c, hipGetLastError(), "kernel launch (groups)");
@@ -653,6 +654,7 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
     if (st) return st;
     c->last_attempts = attempt + 1;
     walk_lists_device(W, grid, c->stream);
+    c->xq_clean = false;
     st = timer_stop(c, c->t_walk);
     if (st) return st;
     st = hip_check(c, hipGetLastError(), "kernel launch (walk)");
@@ -1106,7 +1108,8 @@ static bh_status features_common(bh_ctx *c, const double *eps_sys, float *feat) 
   pa.nsys = c->nsys;
   pa.feat = feat;
   if (c->probe_bpc == 0) c->probe_bpc = probe_blocks_per_cu();
-  probe_device(pa, c->num_cu * c->probe_bpc, c->stream);
+  probe_device(pa, c->num_cu * c->probe_bpc, !c->xq_clean, c->stream);
+  c->xq_clean = false;
   return hip_check(c, hipGetLastError(), "kernel launch (features)");
 }
 

@@ -163,6 +163,7 @@ struct bh_ctx {
   int32_t nsys = 0;
   bool have_tree = false;
   bool have_groups = false;
+  bool xq_clean = false;  // the per-XCD group queues are known to be 0 (reset by make_groups, used by walks)
   bool have_forces = false;
   bool have_quad = false;  // the current tree carries second moments
   bool have_neighbors = false;  // a neighbour search ran since the last build
@@ -416,7 +417,8 @@ struct ProbeArgs {
   int nsys;
   float *feat;        // [G][12]
 };
-void probe_device(const ProbeArgs &a, int grid, hipStream_t s);
+// reset: clear the per-XCD group queues first (not needed right after make_groups)
+void probe_device(const ProbeArgs &a, int grid, bool reset, hipStream_t s);
 int probe_blocks_per_cu();
 int walk_lists_blocks_per_cu();  // resident single-wave blocks per CU
 

@@ -874,8 +874,8 @@ int probe_blocks_per_cu() {
   return b;
 }
 
-void probe_device(const ProbeArgs &a, int grid, hipStream_t s) {
-  k_reset_queue<<<1, 1, 0, s>>>(a.info);
+void probe_device(const ProbeArgs &a, int grid, bool reset, hipStream_t s) {
+  if (reset) k_reset_queue<<<1, 1, 0, s>>>(a.info);
   k_probe<<<(unsigned)grid, kWave, 0, s>>>(a);
 }
 
