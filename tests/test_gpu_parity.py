@@ -46,6 +46,33 @@ def test_sorted_keys_and_permutation_bit_exact(gpu, name):
     assert np.array_equal(perm.cpu().numpy().astype(np.int64), perm_o)
 
 
+def _many_tile_inputs(kind):
+    if kind == "clustered":
+        return inputs.clustered(600_000, 31, n_halos=200)[0]
+    # 8192 distinct points, each repeated 32 times in shuffled order: long
+    # runs of equal keys that cross tile boundaries, where only the input
+    # order separates them (the sort must be stable)
+    rng = np.random.default_rng(32)
+    base = rng.uniform(0.0, 1.0, (8192, 3))
+    return base[rng.permutation(np.repeat(np.arange(8192), 32))]
+
+
+@pytest.mark.parametrize("kind", ["clustered", "repeated"])
+def test_sort_across_many_tiles_bit_exact(gpu, kind):
+    """Hundreds of 4096-key tiles per pass (147 and 64), so that a tile's
+    offsets come from look-backs over several windows of earlier tiles that
+    run at the same time."""
+    pos = _many_tile_inputs(kind)
+    mass = np.full(pos.shape[0], 1.0 / pos.shape[0])
+    keys_o, perm_o = oracle.Tree(pos, mass).sorted()
+    c = gpu.Context()
+    c.build_tree(to_dev(pos), to_dev(mass))
+    keys, perm = c.export_sorted()
+    assert c.get_stats().error_flags == 0
+    assert np.array_equal(keys.cpu().numpy().view(np.uint64), keys_o)
+    assert np.array_equal(perm.cpu().numpy().astype(np.int64), perm_o)
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_tree_matches_oracle(gpu, name):
     pos, eps, theta, n_crit = CASES[name]
