@@ -205,40 +205,52 @@ __global__ void k_delta(const uint64_t *__restrict__ keys, const int32_t *__rest
 
 // owner[j]: the owning position of the cell split at j (its first split), or
 // the first particle of the run of equal keys containing j; level[j]: level
-// of the cell owned at j, -1 when j owns none.
+// of the cell owned at j, -1 when j owns none; for an owned cell also its
+// particle range (cfirst, ccount).
 __global__ void k_owner(const uint64_t *__restrict__ keys, const int8_t *__restrict__ delta, int64_t n,
                         const SysInfo *__restrict__ sys, int nsys, int32_t *__restrict__ owner,
-                        int8_t *__restrict__ level) {
+                        int8_t *__restrict__ level, int32_t *__restrict__ cfirst, int32_t *__restrict__ ccount) {
   int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (jj >= n) return;
   const int j = (int)jj;
   const int d = delta[j];
-  int own = -1, lev = -1;
+  int own = -1, lev = -1, a = 0, b = -1;
   if (d >= 0) {
     const int s = system_of(sys, nsys, j);
-    const int lo = sys[s].first;
+    const int lo = sys[s].first, hi = lo + sys[s].count;
     const uint64_t kj = keys[j];
     if (d < kKeyLevels) {
       const int sh = prefix_shift(d);
-      int a = gallop_first(keys, lo, j, kj >> sh, sh);
+      a = gallop_first(keys, lo, j, kj >> sh, sh);
       const int sh1 = prefix_shift(d + 1);
       int e = gallop_past(keys, a, j + 1, keys[a] >> sh1, sh1);
       own = e - 1;
-      if (own == j) lev = d;
+      if (own == j) {
+        lev = d;
+        b = gallop_past(keys, j, hi, kj >> sh, sh) - 1;
+      }
     } else {
       own = gallop_first(keys, lo, j, kj, 0);
-      if (j == lo || delta[j - 1] != kKeyLevels) lev = kKeyLevels;
+      if (j == lo || delta[j - 1] != kKeyLevels) {
+        lev = kKeyLevels;
+        a = j;
+        b = gallop_past(keys, j, hi, kj, 0) - 1;
+      }
     }
   }
   owner[j] = own;
   level[j] = (int8_t)lev;
+  if (lev >= 0) {
+    cfirst[j] = a;
+    ccount[j] = b - a + 1;
+  }
 }
 
-// Range, parent and octant of every owned cell; octant masks of the parents.
+// Parent and octant of every owned cell; octant masks of the parents.
 __global__ void k_cells(const uint64_t *__restrict__ keys, const int8_t *__restrict__ delta,
                         const int32_t *__restrict__ owner, const int8_t *__restrict__ level, int64_t n,
-                        const SysInfo *__restrict__ sys, int nsys, int32_t *__restrict__ cfirst,
-                        int32_t *__restrict__ ccount, int32_t *__restrict__ cparent, int8_t *__restrict__ cdigit,
+                        const SysInfo *__restrict__ sys, int nsys, const int32_t *__restrict__ cfirst,
+                        const int32_t *__restrict__ ccount, int32_t *__restrict__ cparent, int8_t *__restrict__ cdigit,
                         int32_t *__restrict__ mask, DevInfo *info) {
   int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (jj >= n) return;
@@ -246,19 +258,8 @@ __global__ void k_cells(const uint64_t *__restrict__ keys, const int8_t *__restr
   const int l = level[j];
   if (l < 0) return;
   const int s = system_of(sys, nsys, j);
-  const int lo = sys[s].first, hi = lo + sys[s].count;
-  const uint64_t kj = keys[j];
-  int a, b;
-  if (l < kKeyLevels) {
-    const int sh = prefix_shift(l);
-    a = gallop_first(keys, lo, j, kj >> sh, sh);
-    b = gallop_past(keys, j, hi, kj >> sh, sh) - 1;
-  } else {
-    a = j;
-    b = gallop_past(keys, j, hi, kj, 0) - 1;
-  }
-  cfirst[j] = a;
-  ccount[j] = b - a + 1;
+  const int lo = sys[s].first;
+  const int a = cfirst[j], b = a + ccount[j] - 1;
   const int dl = (a > lo) ? delta[a - 1] : -1;
   const int dr = delta[b];
   const int lp = max(dl, dr);
@@ -610,7 +611,7 @@ void build_tree_device(TreeBuffers &B, hipStream_t s) {
   B.sorted_keys = B.keys[cur];
   k_gather<<<blocks_for(n), 256, 0, s>>>(B.vals[cur], B.pos, B.mass, n, B.spos, B.smass, B.perm);
   k_delta<<<blocks_for(n), 256, 0, s>>>(keys, B.perm, nsys > 1 ? B.sys_in : nullptr, n, B.delta);
-  k_owner<<<blocks_for(n), 256, 0, s>>>(keys, B.delta, n, B.sys, nsys, B.owner, B.level);
+  k_owner<<<blocks_for(n), 256, 0, s>>>(keys, B.delta, n, B.sys, nsys, B.owner, B.level, B.cfirst, B.ccount);
   fill_i32(B.mask, 0, n, s);
   k_cells<<<blocks_for(n), 256, 0, s>>>(keys, B.delta, B.owner, B.level, n, B.sys, nsys, B.cfirst, B.ccount,
                                          B.cparent, B.cdigit, B.mask, B.info);
