@@ -258,7 +258,7 @@ static bh_status check_device_errors(bh_ctx *c) {
   if (e & kErrBuild) return fail(c, BH_EINTERNAL, "tree build produced an inconsistent node layout");
   if (e & kErrStack) return fail(c, BH_EINTERNAL, "walk stack capacity exceeded or node range corrupt");
   if (e & kErrPool) return fail(c, BH_EINTERNAL, "interaction list pool exhausted");
-  if (e & kErrWait) return fail(c, BH_EINTERNAL, "walk task wait timed out");
+  if (e & kErrWait) return fail(c, BH_EINTERNAL, "a bounded device wait timed out (walk task or sort look-back)");
   if (e & kErrRadius) return fail(c, BH_EINVAL, "search radius h must be positive and finite");
   if (e & kErrListSpace) return fail(c, BH_EINVAL, "neighbour list offsets do not match the neighbour counts");
   return BH_OK;

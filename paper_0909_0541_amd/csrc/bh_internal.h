@@ -95,7 +95,7 @@ enum : int32_t {
   kErrTheta = 8,
   kErrBuild = 16,
   kErrPool = 32,
-  kErrWait = 64,
+  kErrWait = 64,          // a bounded wait ended without its condition (walk tasks, sort look-back)
   kErrRadius = 128,      // neighbour search: a radius not positive and finite
   kErrListSpace = 256,   // neighbour search: offsets leave a list too little or too much room
 };
