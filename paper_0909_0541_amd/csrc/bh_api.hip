@@ -400,7 +400,7 @@ void bh_destroy(bh_ctx *c) {
                     &c->hist, &c->nodes, &c->msum, &c->meta, &c->levels, &c->lcells, &c->gflag, &c->gidx, &c->glen, &c->ginfo, &c->gbox, &c->glist,
                     &c->gmass, &c->bbox_part, &c->sys, &c->par, &c->info, &c->direct_part, &c->energy_part,
                     &c->glists, &c->far_pool, &c->near_pool, &c->far_next, &c->near_next,
-                    &c->items, &c->item_n, &c->item_off, &c->feps, &c->mlp_work, &c->mlp_feat, &c->pp_next, &c->order_hist, &c->item_order, &c->tasks, &c->ranges, &c->segs,
+                    &c->items, &c->feps, &c->mlp_work, &c->mlp_feat, &c->pp_next, &c->order_hist, &c->tasks, &c->ranges, &c->segs,
                     &c->split_ctr, &c->gsplit, &c->gnseg, &c->gsegfirst, &c->skeys[0], &c->skeys[1], &c->svals[0],
                     &c->svals[1], &c->shist, &c->sscan, &c->srows, &c->spbase, &c->sgroups, &c->psum,
                     &c->qmom, &c->qpack, &c->far_slot, &c->walk_hist};
@@ -595,7 +595,11 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
     c->range_cap = 1 << 16;
     c->seg_cap = 4096;
   }
-  st = ensure(c, c->order_hist, order_hist_bytes(), "queue order bins");
+  if (!c->order_hist.p) {
+    st = ensure(c, c->order_hist, order_hist_bytes(), "queue order bins");
+    if (st) return st;
+    order_clear_device(P<int32_t>(c->order_hist), c->stream);  // every later call leaves it zero
+  }
   if (st) return st;
   SplitBuffers S{};
   int32_t nsegs_host = 0;
@@ -717,15 +721,6 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
   const size_t icap = gcap + gcap / 64 + 64 + (size_t)4 * c->seg_cap;  // items: blocks of 64, segments
   st = ensure(c, c->items, 2 * sizeof(int32_t) * icap, "force items");
   if (st) return st;
-  st = ensure(c, c->item_n, sizeof(int32_t) * gcap, "force item counts");
-  if (st) return st;
-  st = ensure(c, c->item_off, sizeof(int32_t) * gcap, "force item offsets");
-  if (st) return st;
-  st = ensure(c, c->item_order, sizeof(int32_t) * icap, "force order");
-  if (st) return st;
-  force_items_device(P<int32_t>(c->ginfo), P<int32_t>(c->gsplit), P<int32_t>(c->gnseg), P<int32_t>(c->glist),
-                     P<DevInfo>(c->info), (int64_t)gcap, P<int32_t>(c->item_n), P<int32_t>(c->item_off), P<int32_t>(c->items),
-                     c->scan_tmp.p, P<int32_t>(c->walk_hist), c->stream);
   ForceArgs F{};
   F.items = P<int32_t>(c->items);
   F.ginfo = P<int32_t>(c->ginfo);
@@ -746,7 +741,6 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
   F.acc = acc;
   F.pot = pot;
   F.info = P<DevInfo>(c->info);
-  F.order = P<int32_t>(c->item_order);
   F.xstart = P<int32_t>(c->order_hist) + (order_hist_bytes() / sizeof(int32_t) - 16);
   F.glist = P<int32_t>(c->glist);
   F.segs = S.segs;
@@ -754,8 +748,8 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
   F.gsegfirst = S.gsegfirst;
   F.pbase = S.pbase;
   F.psum = split ? P<double>(c->psum) : nullptr;
-  item_order_device(F, P<int32_t>(c->item_n), P<int32_t>(c->item_off), (int64_t)gcap, P<int32_t>(c->order_hist),
-                    P<int32_t>(c->item_order), c->stream);
+  item_order_device(F, P<int32_t>(c->gsplit), P<int32_t>(c->gnseg), (int64_t)gcap, P<int32_t>(c->order_hist),
+                    P<int32_t>(c->walk_hist), P<int32_t>(c->items), c->stream);
   st = timer_start(c, c->t_force);
   if (st) return st;
   force_lists_device(F, fgrid, c->stream);

@@ -207,7 +207,7 @@ struct bh_ctx {
   bh::DevBuf gbox;              // FP64 [G][6]
   bh::DevBuf glist;             // int32 [G] list length of the last force call
   bh::DevBuf glists;            // int32 [G][4] far head, far count, near head, near count
-  bh::DevBuf items, item_n, item_off;  // force work items and their per-group counts / offsets
+  bh::DevBuf items;             // force work items in queue order
   bh::DevBuf far_pool, near_pool;  // list chunks
   bh::DevBuf far_next, near_next;  // int32 chunk links
   int32_t far_cap = 0, near_cap = 0;  // pool capacities in chunks
@@ -226,7 +226,6 @@ struct bh_ctx {
   bh::DevBuf pp_next;           // int32 per slot: thread pointers of the per-particle walk
   bh::DevBuf order_hist;        // int32 cost bins of the queue orders
   bh::DevBuf walk_hist;         // int32 [4]: mean list length of the last force call (automatic split cap)
-  bh::DevBuf item_order;        // int32 queue position -> force item (longest first)
   // split walks: tasks (ping-pong), range pool, segments, counters, per-group
   // flags, segment sort and partial sums
   bh::DevBuf tasks, ranges, segs, split_ctr, gsplit, gnseg, gsegfirst;
@@ -438,8 +437,8 @@ struct ForceArgs {
   float *acc;
   float *pot;
   DevInfo *info;
-  const int32_t *items;  // [n_items][2] group, member block (+ 256 x (segment + 1) for a split group)
-  const int32_t *order;  // queue position -> item: eight per-XCD queues, longest group first
+  const int32_t *items;  // [n_items][2] in queue order (eight per-XCD queues, longest group first):
+                         // group, member block (+ 256 x (segment + 1) for a split group)
   const int32_t *xstart; // [9]: first queue position of each XCD's queue, then the item count
   const int32_t *glist;  // [G] list length of each group (all segments)
   // split groups: segments sorted by (group, key), the first sorted segment
@@ -453,12 +452,13 @@ struct ForceArgs {
   const int32_t *far_slot;    // quadrupole sums: node slot of each far entry (near entries: residue .w)
   const float4 *qpack;        // quadrupole sums: [slots][2] second moments
 };
-void force_items_device(const int32_t *ginfo, const int32_t *gsplit, const int32_t *gnseg, const int32_t *glist,
-                        DevInfo *info, int64_t cap, int32_t *nblk, int32_t *off, int32_t *items, void *scan_tmp,
-                        int32_t *mean_list, hipStream_t s);
 void force_lists_device(const ForceArgs &a, int grid, hipStream_t s);
-void item_order_device(const ForceArgs &f, const int32_t *nblk, const int32_t *item_off, int64_t gcap, int32_t *hist,
-                       int32_t *order, hipStream_t s);
+// The force items in queue order (k_order.hip), with the list statistics and
+// the mean list length; hist holds order_hist_bytes() and is zero on entry
+// (order_clear_device once after allocation; every call leaves it zero).
+void item_order_device(const ForceArgs &f, const int32_t *gsplit, const int32_t *gnseg, int64_t gcap, int32_t *hist,
+                       int32_t *mean_list, int32_t *items, hipStream_t s);
+void order_clear_device(int32_t *hist, hipStream_t s);
 int force_lists_blocks_per_cu(bool quad);
 void reset_list_counters(DevInfo *info, hipStream_t s);
 

@@ -262,7 +262,7 @@ __global__ __launch_bounds__(kWave) void k_force_lists(ForceArgs a, const float4
       const int s0 = a.xstart[x], s1 = a.xstart[x + 1];
       const int q = take_one(&a.info->fq[x * kLineInts], lane);
       if (s0 + q < s1) {
-        it = __builtin_amdgcn_readfirstlane(a.order[s0 + q]);
+        it = s0 + q;
         break;
       }
       ++tried;
@@ -370,76 +370,7 @@ __global__ __launch_bounds__(kWave) void k_force_lists(ForceArgs a, const float4
   }
 }
 
-// Member blocks per group (ceil(count / 64)), times the segments of a split
-// group; and the list statistics (interactions, entries, longest list), one
-// atomic per wave rather than per group.
-__global__ __launch_bounds__(256) void k_item_counts(const int32_t *__restrict__ ginfo,
-                                                     const int32_t *__restrict__ gsplit,
-                                                     const int32_t *__restrict__ gnseg,
-                                                     const int32_t *__restrict__ glist, DevInfo *__restrict__ info,
-                                                     int64_t cap, int32_t *__restrict__ nblk) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int G = info->n_groups;
-  if ((int64_t)blockIdx.x * blockDim.x >= cap) return;  // whole block
-  int nb = 0;
-  unsigned long long inter = 0, entries = 0;
-  int longest = 0;
-  if (g < G) {
-    const int c = ginfo[3 * g + 1];
-    nb = (c + kWave - 1) / kWave;
-    if (gsplit[g]) nb *= gnseg[g];
-    const int len = glist[g];
-    inter = (unsigned long long)c * (unsigned long long)max(len - 1, 0);
-    entries = (unsigned long long)len;
-    longest = len;
-  }
-  if (g < cap) nblk[g] = nb;
-  if ((int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(kWave - 1)) >= G) return;  // whole wave past the groups
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    inter += __shfl_xor(inter, d, kWave);
-    entries += __shfl_xor(entries, d, kWave);
-    longest = max(longest, __shfl_xor(longest, d, kWave));
-  }
-  if (lane_id() == 0) {
-    atomicAdd(&info->interactions, inter);
-    atomicAdd(&info->list_entries, entries);
-    atomicMax(&info->max_list, longest);
-  }
-}
-
-// Items as (group, member block + 256 x (segment + 1) for a split group);
-// and the mean list length of this call, for the next walk's split cap.
-__global__ void k_item_fill(const int32_t *__restrict__ ginfo, const int32_t *__restrict__ gsplit,
-                            const int32_t *__restrict__ gnseg, const int32_t *__restrict__ off,
-                            const DevInfo *__restrict__ info, int32_t *__restrict__ items,
-                            int32_t *__restrict__ mean_list) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g == 0 && mean_list) {
-    const unsigned long long G = (unsigned long long)max(info->n_groups, 1);
-    mean_list[0] = (int32_t)min(info->list_entries / G, (unsigned long long)(INT32_MAX / 64));
-  }
-  if (g >= info->n_groups) return;
-  const int nb = (ginfo[3 * g + 1] + kWave - 1) / kWave;
-  const int ns = gsplit[g] ? gnseg[g] : 0;
-  int64_t k = off[g];
-  for (int s = 0; s < (ns ? ns : 1); ++s)
-    for (int b = 0; b < nb; ++b, ++k) {
-      items[2 * k] = (int32_t)g;
-      items[2 * k + 1] = b + (ns ? 256 * (s + 1) : 0);
-    }
-}
-
 }  // namespace
-
-void force_items_device(const int32_t *ginfo, const int32_t *gsplit, const int32_t *gnseg, const int32_t *glist,
-                        DevInfo *info, int64_t cap, int32_t *nblk, int32_t *off, int32_t *items, void *scan_tmp,
-                        int32_t *mean_list, hipStream_t s) {
-  const unsigned blocks = (unsigned)((cap + 255) / 256);
-  k_item_counts<<<blocks, 256, 0, s>>>(ginfo, gsplit, gnseg, glist, info, cap, nblk);
-  scan_exclusive_i32(nblk, off, cap, &info->n_items, scan_tmp, s);
-  k_item_fill<<<blocks, 256, 0, s>>>(ginfo, gsplit, gnseg, off, info, items, mean_list);
-}
 
 int force_lists_blocks_per_cu(bool quad) {
   int b = 0;

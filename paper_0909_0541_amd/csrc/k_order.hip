@@ -14,7 +14,8 @@
 // others.  The order is a counting sort of the groups over (XCD, cost bin),
 // each group weighted by its item count; cost bin = list length / lane
 // partitions of its first block / 128.  The order within a bin does not
-// change any result: every item computes its own outputs.
+// change any result: every item computes its own outputs.  The items are
+// written straight into their queue places.
 #include <algorithm>
 
 #include "bh_device.h"
@@ -42,25 +43,57 @@ __global__ void k_order_clear(int32_t *hist) {
   for (int b = threadIdx.x; b < kKeys; b += blockDim.x) hist[b] = 0;
 }
 
-// Item counts per (XCD, bin).
-__global__ __launch_bounds__(256) void k_order_hist(ForceArgs f, const int32_t *__restrict__ nblk, int64_t cap,
+// Work items of group g: ceil(count / 64) member blocks, times the segments
+// of a split group.
+__device__ __forceinline__ int group_items(const ForceArgs &f, const int32_t *__restrict__ gsplit,
+                                           const int32_t *__restrict__ gnseg, int g) {
+  const int nb = (f.ginfo[3 * g + 1] + kWave - 1) / kWave;
+  return gsplit[g] ? nb * gnseg[g] : nb;
+}
+
+// Item counts per (XCD, bin) into hist (zero on entry), and the list
+// statistics (interactions, entries, longest list), one atomic per wave.
+__global__ __launch_bounds__(256) void k_order_hist(ForceArgs f, const int32_t *__restrict__ gsplit,
+                                                    const int32_t *__restrict__ gnseg, int64_t cap,
                                                     int32_t *__restrict__ hist) {
   __shared__ int32_t h[kKeys];
   for (int b = threadIdx.x; b < kKeys; b += blockDim.x) h[b] = 0;
   __syncthreads();
   const int64_t G = min<int64_t>(f.info->n_groups, cap);
   const int64_t t0 = (int64_t)blockIdx.x * kTile;
-  for (int64_t g = t0 + threadIdx.x; g < G && g < t0 + kTile; g += blockDim.x)
-    if (nblk[g] > 0) atomicAdd(&h[group_key(f, (int)g)], nblk[g]);
+  unsigned long long inter = 0, entries = 0;
+  int longest = 0;
+  for (int64_t g = t0 + threadIdx.x; g < G && g < t0 + kTile; g += blockDim.x) {
+    const int nb = group_items(f, gsplit, gnseg, (int)g);
+    if (nb > 0) atomicAdd(&h[group_key(f, (int)g)], nb);
+    const int c = f.ginfo[3 * g + 1], len = f.glist[g];
+    inter += (unsigned long long)c * (unsigned long long)max(len - 1, 0);
+    entries += (unsigned long long)max(len, 0);
+    longest = max(longest, len);
+  }
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    inter += __shfl_xor(inter, d, kWave);
+    entries += __shfl_xor(entries, d, kWave);
+    longest = max(longest, __shfl_xor(longest, d, kWave));
+  }
+  if (lane_id() == 0 && (inter || entries || longest)) {
+    atomicAdd(&f.info->interactions, inter);
+    atomicAdd(&f.info->list_entries, entries);
+    atomicMax(&f.info->max_list, longest);
+  }
   __syncthreads();
   for (int b = threadIdx.x; b < kKeys; b += blockDim.x)
     if (h[b]) atomicAdd(&hist[b], h[b]);
 }
 
-// Exclusive scan of the bins in place (one block of 1024 threads, kKeys /
-// 1024 bins each); xstart[x] = first queue position of XCD x, xstart[8] the
-// item count.
-__global__ __launch_bounds__(1024) void k_order_scan(int32_t *__restrict__ hist, int32_t *__restrict__ xstart) {
+// Exclusive scan of the bins (one block of 1024 threads, kKeys / 1024 bins
+// each) into the cursors; hist is left zero for the next call.  xstart[x] =
+// first queue position of XCD x, xstart[8] the item count; mean_list (when
+// set) = this call's mean list length, for the next walk's split cap.
+__global__ __launch_bounds__(1024) void k_order_scan(int32_t *__restrict__ hist, int32_t *__restrict__ cursor,
+                                                     int32_t *__restrict__ xstart, const DevInfo *__restrict__ info,
+                                                     int32_t *__restrict__ mean_list) {
   constexpr int kPer = kKeys / 1024;
   __shared__ int32_t w[1024 / kWave];
   const int t = threadIdx.x;
@@ -68,6 +101,7 @@ __global__ __launch_bounds__(1024) void k_order_scan(int32_t *__restrict__ hist,
 #pragma unroll
   for (int j = 0; j < kPer; ++j) {
     v[j] = hist[t * kPer + j];
+    hist[t * kPer + j] = 0;
     s += v[j];
   }
   const int inc = wave_inclusive_sum(s);
@@ -80,17 +114,22 @@ __global__ __launch_bounds__(1024) void k_order_scan(int32_t *__restrict__ hist,
   for (int j = 0; j < kPer; ++j) {
     const int b = t * kPer + j;
     if (b % kBins == 0) xstart[b / kBins] = off;
-    hist[b] = off;
+    cursor[b] = off;
     off += v[j];
   }
   if (t == 1023) xstart[kXcd] = off;
+  if (t == 0 && mean_list) {
+    const unsigned long long G = (unsigned long long)max(info->n_groups, 1);
+    mean_list[0] = (int32_t)min(info->list_entries / G, (unsigned long long)(INT32_MAX / 64));
+  }
 }
 
-// Each group takes a run of nblk[g] queue places from its bin's cursor and
-// lists its items there in order (item_off[g] + b).
-__global__ __launch_bounds__(256) void k_order_scatter(ForceArgs f, const int32_t *__restrict__ nblk,
-                                                       const int32_t *__restrict__ item_off, int64_t cap,
-                                                       int32_t *__restrict__ cursor, int32_t *__restrict__ order) {
+// Each group takes a run of queue places from its bin's cursor and writes
+// its items there: (group, member block + 256 x (segment + 1) for a split
+// group), segments in order, blocks in order within a segment.
+__global__ __launch_bounds__(256) void k_order_scatter(ForceArgs f, const int32_t *__restrict__ gsplit,
+                                                       const int32_t *__restrict__ gnseg, int64_t cap,
+                                                       int32_t *__restrict__ cursor, int32_t *__restrict__ items) {
   constexpr int kPer = kTile / 256;
   __shared__ int32_t cnt[kKeys], base[kKeys];
   const int64_t G = min<int64_t>(f.info->n_groups, cap);
@@ -98,14 +137,18 @@ __global__ __launch_bounds__(256) void k_order_scatter(ForceArgs f, const int32_
   if (t0 >= G) return;
   for (int b = threadIdx.x; b < kKeys; b += blockDim.x) cnt[b] = 0;
   __syncthreads();
-  int key[kPer], rank[kPer];
+  int key[kPer], rank[kPer], nbk[kPer];
 #pragma unroll
   for (int j = 0; j < kPer; ++j) {
     const int64_t g = t0 + j * 256 + threadIdx.x;
     key[j] = -1;
-    if (g < G && nblk[g] > 0) {
-      key[j] = group_key(f, (int)g);
-      rank[j] = atomicAdd(&cnt[key[j]], nblk[g]);
+    nbk[j] = 0;
+    if (g < G) {
+      nbk[j] = group_items(f, gsplit, gnseg, (int)g);
+      if (nbk[j] > 0) {
+        key[j] = group_key(f, (int)g);
+        rank[j] = atomicAdd(&cnt[key[j]], nbk[j]);
+      }
     }
   }
   __syncthreads();
@@ -114,25 +157,32 @@ __global__ __launch_bounds__(256) void k_order_scatter(ForceArgs f, const int32_
 #pragma unroll
   for (int j = 0; j < kPer; ++j) {
     if (key[j] < 0) continue;
-    const int64_t g = t0 + j * 256 + threadIdx.x;
-    const int p = base[key[j]] + rank[j], first = item_off[g];
-    for (int b = 0; b < nblk[g]; ++b) order[p + b] = first + b;
+    const int g = (int)(t0 + j * 256 + threadIdx.x);
+    const int nb = (f.ginfo[3 * g + 1] + kWave - 1) / kWave;
+    const int ns = gsplit[g] ? gnseg[g] : 0;
+    int64_t p = base[key[j]] + rank[j];
+    for (int sg = 0; sg < (ns ? ns : 1); ++sg)
+      for (int b = 0; b < nb; ++b, ++p) {
+        items[2 * p] = g;
+        items[2 * p + 1] = b + (ns ? 256 * (sg + 1) : 0);
+      }
   }
 }
 
 }  // namespace
 
-size_t order_hist_bytes() { return sizeof(int32_t) * (kKeys + 16); }
+size_t order_hist_bytes() { return sizeof(int32_t) * (2 * kKeys + 16); }
 
-void item_order_device(const ForceArgs &f, const int32_t *nblk, const int32_t *item_off, int64_t gcap, int32_t *hist,
-                       int32_t *order, hipStream_t s) {
+void order_clear_device(int32_t *hist, hipStream_t s) { k_order_clear<<<1, 256, 0, s>>>(hist); }
+
+void item_order_device(const ForceArgs &f, const int32_t *gsplit, const int32_t *gnseg, int64_t gcap, int32_t *hist,
+                       int32_t *mean_list, int32_t *items, hipStream_t s) {
   if (gcap <= 0) return;
   const unsigned grid = (unsigned)((gcap + kTile - 1) / kTile);
-  int32_t *xstart = hist + kKeys;
-  k_order_clear<<<1, 256, 0, s>>>(hist);
-  k_order_hist<<<grid, 256, 0, s>>>(f, nblk, gcap, hist);
-  k_order_scan<<<1, 1024, 0, s>>>(hist, xstart);
-  k_order_scatter<<<grid, 256, 0, s>>>(f, nblk, item_off, gcap, hist, order);
+  int32_t *cursor = hist + kKeys, *xstart = hist + 2 * kKeys;
+  k_order_hist<<<grid, 256, 0, s>>>(f, gsplit, gnseg, gcap, hist);
+  k_order_scan<<<1, 1024, 0, s>>>(hist, cursor, xstart, f.info, mean_list);
+  k_order_scatter<<<grid, 256, 0, s>>>(f, gsplit, gnseg, gcap, cursor, items);
 }
 
 }  // namespace bh
