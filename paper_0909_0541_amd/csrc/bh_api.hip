@@ -326,6 +326,8 @@ static bh_status build_common(bh_ctx *c, int32_t nsys, const int64_t *offsets, c
   B.lcells = P<int32_t>(c->lcells);
   B.slot_cap = (int64_t)std::min({c->nodes.bytes / sizeof(NodeRec), c->msum.bytes / 32, c->meta.bytes});
   B.curve = c->opt.curve;
+  B.any_empty = false;
+  for (int s = 0; s < nsys; ++s) B.any_empty |= c->sys_host[s].count == 0;
   const bool quad = c->opt.quadrupole != 0;
   if (quad) {
     const size_t slots = (size_t)B.slot_cap;

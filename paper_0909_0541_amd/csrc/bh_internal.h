@@ -298,6 +298,7 @@ struct TreeBuffers {
   float4 *qpack;          // with qmom: FP32 [slots][2] 3 (xx, yy, zz, xy), (3 xz, 3 yz, T, 1.5 T), T the trace
   int8_t *meta;           // per slot: 32 * kind + level (export only)
   int curve;              // key order: 0 Morton, 1 Peano-Hilbert
+  bool any_empty;         // some system holds no particle (its root record is written apart)
   int32_t *lcount, *loff, *lcursor;  // cells per level: counts, offsets [23], scatter cursors
   int32_t *lcells;                   // cell owner positions grouped by level
   int64_t slot_cap;       // capacity of nodes/msum/meta in slots

@@ -175,9 +175,18 @@ __global__ void k_keys(const double *__restrict__ pos, const double *__restrict_
   if (!(m >= 0.0) || !isfinite(m)) atomicOr(&info->err, kErrBadMass);
 }
 
-__global__ void k_gather(const uint32_t *__restrict__ vals, const double *__restrict__ pos, const double *__restrict__ mass,
-                         int64_t n, double *__restrict__ spos, double *__restrict__ smass, int32_t *__restrict__ perm) {
+// Sorted copies and the inverse permutation; the split depth delta_i of each
+// pair of neighbouring keys (-1 across a system boundary or at the end); the
+// octant masks cleared for the topology pass and the level counters for the
+// level pass.
+__global__ void k_gather(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
+                         const double *__restrict__ pos, const double *__restrict__ mass, int64_t n,
+                         const int32_t *__restrict__ sys_in, double *__restrict__ spos, double *__restrict__ smass,
+                         int32_t *__restrict__ perm, int8_t *__restrict__ delta, int32_t *__restrict__ mask,
+                         int32_t *__restrict__ lcount) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0)
+    for (int l = 0; l < 72; ++l) lcount[l] = 0;  // counts, offsets, cursors
   if (i >= n) return;
   uint32_t j = vals[i];
   perm[i] = (int32_t)j;
@@ -185,23 +194,18 @@ __global__ void k_gather(const uint32_t *__restrict__ vals, const double *__rest
   spos[3 * i + 1] = pos[3 * (int64_t)j + 1];
   spos[3 * i + 2] = pos[3 * (int64_t)j + 2];
   smass[i] = mass[j];
+  int d = -1;
+  if (i + 1 < n) {
+    const bool same = sys_in ? (sys_in[j] == sys_in[vals[i + 1]]) : true;
+    if (same) d = common_digits(keys[i], keys[i + 1]);
+  }
+  delta[i] = (int8_t)d;
+  mask[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
 // topology
 // ---------------------------------------------------------------------------
-
-__global__ void k_delta(const uint64_t *__restrict__ keys, const int32_t *__restrict__ perm,
-                        const int32_t *__restrict__ sys_in, int64_t n, int8_t *__restrict__ delta) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int d = -1;
-  if (i + 1 < n) {
-    bool same = sys_in ? (sys_in[perm[i]] == sys_in[perm[i + 1]]) : true;
-    if (same) d = common_digits(keys[i], keys[i + 1]);
-  }
-  delta[i] = (int8_t)d;
-}
 
 // owner[j]: the owning position of the cell split at j (its first split), or
 // the first particle of the run of equal keys containing j; level[j]: level
@@ -422,27 +426,31 @@ __global__ __launch_bounds__(256) void k_level_count(const int8_t *__restrict__ 
   if (threadIdx.x <= kKeyLevels && c[threadIdx.x]) atomicAdd(&lcount[threadIdx.x], c[threadIdx.x]);
 }
 
-__global__ void k_level_offsets(const int32_t *__restrict__ lcount, int32_t *__restrict__ loff,
-                                int32_t *__restrict__ lcursor, DevInfo *info) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int32_t s = 0, deepest = 0;
-  for (int l = 0; l <= kKeyLevels; ++l) {
-    loff[l] = s;
-    lcursor[l] = s;
-    s += lcount[l];
-    if (lcount[l]) deepest = l;
-  }
-  loff[kKeyLevels + 1] = s;
-  info->n_cells = s;
-  info->max_level = deepest;
-}
-
+// Each block takes the level offsets from the counts (block 0 also stores
+// them, the cell count and the deepest level); rank = level offset + block
+// base (one global atomic per block and level on the zeroed cursors) + wave
+// base (one LDS atomic per wave, level and round) + lanes below with that
+// level.
 __global__ __launch_bounds__(256) void k_level_scatter(const int8_t *__restrict__ level, int64_t n,
-                                                       int32_t *__restrict__ lcursor, int32_t *__restrict__ lcells) {
-  // rank = block base (one global atomic per block and level) + wave base
-  // (one LDS atomic per wave, level and round) + lanes below with that level
-  __shared__ int32_t c[kKeyLevels + 1], base[kKeyLevels + 1];
+                                                       const int32_t *__restrict__ lcount, int32_t *__restrict__ loff,
+                                                       int32_t *__restrict__ lcursor, int32_t *__restrict__ lcells,
+                                                       DevInfo *info) {
+  __shared__ int32_t c[kKeyLevels + 1], base[kKeyLevels + 1], off[kKeyLevels + 2];
   if (threadIdx.x <= kKeyLevels) c[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    int32_t sum = 0, deepest = 0;
+    for (int l = 0; l <= kKeyLevels; ++l) {
+      off[l] = sum;
+      sum += lcount[l];
+      if (lcount[l]) deepest = l;
+    }
+    off[kKeyLevels + 1] = sum;
+    if (blockIdx.x == 0) {
+      for (int l = 0; l <= kKeyLevels + 1; ++l) loff[l] = off[l];
+      info->n_cells = sum;
+      info->max_level = deepest;
+    }
+  }
   __syncthreads();
   const int64_t b0 = (int64_t)blockIdx.x * blockDim.x * kLevelTile;
   int l[kLevelTile], pos[kLevelTile];
@@ -457,16 +465,13 @@ __global__ __launch_bounds__(256) void k_level_scatter(const int8_t *__restrict_
     pos[q] = wbase + rank_below(peers);
   }
   __syncthreads();
-  if (threadIdx.x <= kKeyLevels && c[threadIdx.x]) base[threadIdx.x] = atomicAdd(&lcursor[threadIdx.x], c[threadIdx.x]);
+  if (threadIdx.x <= kKeyLevels && c[threadIdx.x])
+    base[threadIdx.x] = off[threadIdx.x] + atomicAdd(&lcursor[threadIdx.x], c[threadIdx.x]);
   __syncthreads();
   for (int q = 0; q < kLevelTile; ++q) {
     const int64_t j = b0 + (int64_t)q * blockDim.x + threadIdx.x;
     if (l[q] >= 0) lcells[base[l[q]] + pos[q]] = (int32_t)j;
   }
-}
-
-__global__ void k_zero_levels(int32_t *__restrict__ lcount) {
-  if (threadIdx.x <= kKeyLevels && blockIdx.x == 0) lcount[threadIdx.x] = 0;
 }
 
 // Moments of the cells of one level from their children's raw sums.
@@ -609,10 +614,9 @@ void build_tree_device(TreeBuffers &B, hipStream_t s) {
   }
   const uint64_t *keys = B.keys[cur];
   B.sorted_keys = B.keys[cur];
-  k_gather<<<blocks_for(n), 256, 0, s>>>(B.vals[cur], B.pos, B.mass, n, B.spos, B.smass, B.perm);
-  k_delta<<<blocks_for(n), 256, 0, s>>>(keys, B.perm, nsys > 1 ? B.sys_in : nullptr, n, B.delta);
+  k_gather<<<blocks_for(n), 256, 0, s>>>(keys, B.vals[cur], B.pos, B.mass, n, nsys > 1 ? B.sys_in : nullptr, B.spos,
+                                          B.smass, B.perm, B.delta, B.mask, B.lcount);
   k_owner<<<blocks_for(n), 256, 0, s>>>(keys, B.delta, n, B.sys, nsys, B.owner, B.level, B.cfirst, B.ccount);
-  fill_i32(B.mask, 0, n, s);
   k_cells<<<blocks_for(n), 256, 0, s>>>(keys, B.delta, B.owner, B.level, n, B.sys, nsys, B.cfirst, B.ccount,
                                          B.cparent, B.cdigit, B.mask, B.info);
   k_particle_parents<<<blocks_for(n), 256, 0, s>>>(keys, B.delta, B.owner, n, B.sys, nsys, B.pparent, B.pdigit,
@@ -621,11 +625,10 @@ void build_tree_device(TreeBuffers &B, hipStream_t s) {
   scan_exclusive_i32(B.nchild, B.cfc, n, &B.info->n_slots, B.scan_tmp, s);
   k_slots<<<blocks_for(n), 256, 0, s>>>(B.level, B.cparent, B.cdigit, B.pparent, B.pdigit, B.cfc, B.mask, B.spos,
                                          B.smass, n, nsys, B.slot_cap, B.cslot, B.nodes, B.msum, B.meta, B.info);
-  k_empty_roots<<<blocks_for(nsys), 256, 0, s>>>(B.sys, nsys, B.nodes, B.msum, B.meta);
-  k_zero_levels<<<1, 64, 0, s>>>(B.lcount);
+  if (B.any_empty) k_empty_roots<<<blocks_for(nsys), 256, 0, s>>>(B.sys, nsys, B.nodes, B.msum, B.meta);
   k_level_count<<<blocks_for(n, 256 * kLevelTile), 256, 0, s>>>(B.level, n, B.lcount);
-  k_level_offsets<<<1, 64, 0, s>>>(B.lcount, B.loff, B.lcursor, B.info);
-  k_level_scatter<<<blocks_for(n, 256 * kLevelTile), 256, 0, s>>>(B.level, n, B.lcursor, B.lcells);
+  k_level_scatter<<<blocks_for(n, 256 * kLevelTile), 256, 0, s>>>(B.level, n, B.lcount, B.loff, B.lcursor, B.lcells,
+                                                                   B.info);
   const unsigned mgrid = (unsigned)std::min<int64_t>(blocks_for(n), 512);
   for (int lev = kKeyLevels; lev >= 0; --lev)
     k_moments<<<mgrid, 256, 0, s>>>(lev, B.lcells, B.loff, B.level, B.cparent,
