@@ -43,6 +43,30 @@ def test_split_lists_and_forces_match_oracle(gpu, case, cap):
     check_forces(acc, pot, ref)
 
 
+def test_split_with_more_segments_than_the_rank_sort_takes(gpu):
+    """Enough segments (over 16384) that their order comes from the radix
+    sort rather than the small rank sort."""
+    bh = gpu
+    pos, mass = inputs.clustered(100000, 19, n_halos=100)[:2]
+    eps, theta, n_crit = 1e-4, 0.6, 64
+    c = bh.Context(split_visits=64)
+    c, acc, pot, st, G = gpu_run(bh, pos, mass, eps, theta, n_crit, ctx=c)
+    assert st.error_flags == 0 and st.n_segments > 16384
+    t = oracle.Tree(pos, mass)
+    t.groups(n_crit)
+    ref = t.forces(eps, theta)
+    _, _, ll, lm = c.export_groups(lists=True)
+    ll = ll.cpu().numpy()
+    assert np.array_equal(ll, ref["list_len"])
+    # list mass: an FP64 sum of L positive masses, here over many segments
+    # summed in key order; two orders of the same L terms differ by at most
+    # 2 (L - 1) u of the sum (u = 2^-53 each side)
+    lm = lm.cpu().numpy()
+    assert np.all(np.abs(lm - ref["list_mass"]) <= 2.0 * np.maximum(ll - 1, 0) * 2.0**-53 * ref["list_mass"])
+    assert st.interactions == ref["interactions"]
+    check_forces(acc, pot, ref)
+
+
 def test_split_is_deterministic_and_batch_equals_standalone(gpu):
     bh = gpu
     pos, mass, off, eps = inputs.batch_systems(seed=9, n_systems=6, n_min=2000, n_max=20000)
