@@ -103,7 +103,7 @@ __device__ __forceinline__ bool reserve(ChunkList &L, int n, int chunk, ChunkSou
 
 // Chunk holding list position pos (the current one or the one before).
 __device__ __forceinline__ int chunk_of(const ChunkList &L, int pos, int chunk) {
-  return (pos / chunk == L.cap / chunk - 1) ? L.cur : L.prev;
+  return (pos >= L.cap - chunk) ? L.cur : L.prev;  // cap is a multiple of chunk, pos < cap
 }
 
 // Task slots: rcount -1 until published, then the task's range count, or 0
@@ -238,8 +238,10 @@ __device__ __forceinline__ int key_depth(int key) {
 // particles) to 10 % (8M) shorter walks.  SPLIT = false compiles the walk
 // without split walks (no tasks, no hand-over): it holds far fewer registers
 // (29 instead of 77 scalar registers spilled to vector lanes, none to
-// memory) and walks 5 % faster.
-template <bool SPLIT>
+// memory) and walks 5 % faster.  SLOTS: the far entries' node slots are
+// recorded (the quadrupole sums); without them the pool pointer and its test
+// leave the loop.
+template <bool SPLIT, bool SLOTS>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_walk_lists(WalkListArgs a) {
   __shared__ int2 stk[kStack];
   __shared__ int mark[kWave];
@@ -434,7 +436,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) v
             const int pos = F.count + rank_below(fm);
             const int64_t at = (int64_t)chunk_of(F, pos, a.far_tile) * a.far_tile + (pos & (a.far_tile - 1));
             a.far_pool[at] = hi4;
-            if (a.far_slot) a.far_slot[at] = rcur.child < 0 ? -1 : ncur;
+            if (SLOTS) a.far_slot[at] = rcur.child < 0 ? -1 : ncur;
           }
           F.count += nf;
         }
@@ -853,15 +855,24 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(7, 7))) v
 
 int walk_lists_blocks_per_cu() {
   int b = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_walk_lists<true>, kWave, 0) != hipSuccess || b < 1) b = 8;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_walk_lists<true, true>, kWave, 0) != hipSuccess || b < 1)
+    b = 8;
   return b;
 }
 
 void walk_lists_device(const WalkListArgs &a, int grid, hipStream_t s) {
-  if (a.visit_cap > 0)
-    k_walk_lists<true><<<(unsigned)grid, kWave, 0, s>>>(a);
-  else
-    k_walk_lists<false><<<(unsigned)grid, kWave, 0, s>>>(a);
+  const bool slots = a.far_slot != nullptr;
+  if (a.visit_cap > 0) {
+    if (slots)
+      k_walk_lists<true, true><<<(unsigned)grid, kWave, 0, s>>>(a);
+    else
+      k_walk_lists<true, false><<<(unsigned)grid, kWave, 0, s>>>(a);
+  } else {
+    if (slots)
+      k_walk_lists<false, true><<<(unsigned)grid, kWave, 0, s>>>(a);
+    else
+      k_walk_lists<false, false><<<(unsigned)grid, kWave, 0, s>>>(a);
+  }
 }
 
 void split_reset(SplitCounters *ctr, const DevInfo *info, WalkTask *tasks, int task_cap, hipStream_t s) {
