@@ -347,7 +347,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) v
         if (lane < nread) e = stk[sp - 1 - lane];
         const int cnt = (lane < nread) ? e.y : 0;
         const int pre = wave_inclusive_sum(cnt);
-        const int total = __shfl(pre, nread - 1, kWave);
+        const int total = __builtin_amdgcn_readfirstlane(__shfl(pre, nread - 1, kWave));
         bnext = min(starved ? 8 : kWave, total);
         const int start = pre - cnt;
         const int kfull = __popcll(__ballot(lane < nread && pre <= bnext));
@@ -360,7 +360,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) v
         const int e_first = __shfl(e.x, ei < 0 ? 0 : ei, kWave);
         const int nsp = sp - kfull;
         if (kfull < nread) {
-          const int pstart = __shfl(start, kfull, kWave);
+          const int pstart = __builtin_amdgcn_readfirstlane(__shfl(start, kfull, kWave));
           if (pstart < bnext && lane == kfull)
             stk[sp - 1 - kfull] = make_int2(e.x + (bnext - pstart), e.y - (bnext - pstart));
         }
