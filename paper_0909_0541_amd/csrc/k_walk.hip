@@ -233,14 +233,18 @@ __device__ __forceinline__ int key_depth(int key) {
 // task handed over by a walk that reached the visit cap.  Units take chunks
 // for their own list (the group's list unless the walk splits, else a
 // segment).
-// Four waves per SIMD (128 VGPRs, a few spilled) hide more of the node
-// reads' latency than the three that 137 VGPRs allow: measured 5 % (2M
-// particles) to 10 % (8M) shorter walks.  SPLIT = false compiles the walk
-// without split walks (no tasks, no hand-over): it holds far fewer registers
-// (29 instead of 77 scalar registers spilled to vector lanes, none to
-// memory) and walks 5 % faster.  SLOTS: the far entries' node slots are
-// recorded (the quadrupole sums); without them the pool pointer and its test
-// leave the loop.
+// Four waves per SIMD: the split variant needs 128 VGPRs (a few spilled),
+// and four hide more of the node reads' latency than three (measured 5 %
+// (2M particles) to 10 % (8M) shorter walks).  SPLIT = false compiles the
+// walk without split walks (no tasks, no hand-over): 106 VGPRs and 2 scalar
+// registers spilled to vector lanes, 5 % faster than the split variant; at
+// five waves per SIMD (96 VGPRs, a few spilled) it is 1-2 % slower.  The
+// batch size is read as a wave-uniform value, which keeps the batch
+// bookkeeping in scalar registers (it took 16 more VGPRs and 17 more scalar
+// spills, and 11-13 % more time, when the compiler had to treat it as
+// per-lane).  SLOTS: the far entries' node slots are recorded (the
+// quadrupole sums); without them the pool pointer and its test leave the
+// loop.
 template <bool SPLIT, bool SLOTS>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_walk_lists(WalkListArgs a) {
   __shared__ int2 stk[kStack];
