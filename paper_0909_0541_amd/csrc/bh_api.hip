@@ -230,7 +230,7 @@ static bh_status ensure_particles(bh_ctx *c, int64_t n, int nsys) {
       {&c->msum, 32 * slots, "msum"},
       {&c->meta, slots, "meta"},
       {&c->levels, 3 * 24 * sizeof(int32_t), "level table"},
-      {&c->lcells, 4 * N, "cells by level"},
+      {&c->lcells, sizeof(CellRec) * N, "cells by level"},
       {&c->gflag, 4 * N, "gflag"},        {&c->gidx, 4 * N, "gidx"},
       {&c->glen, 4 * N, "glen"},          {&c->ginfo, 12 * N, "ginfo"},
       {&c->gbox, 48 * N, "gbox"},         {&c->glist, 4 * N, "glist"},
@@ -323,7 +323,7 @@ static bh_status build_common(bh_ctx *c, int32_t nsys, const int64_t *offsets, c
   B.lcount = P<int32_t>(c->levels);
   B.loff = B.lcount + 24;
   B.lcursor = B.lcount + 48;
-  B.lcells = P<int32_t>(c->lcells);
+  B.lcells = P<CellRec>(c->lcells);
   B.slot_cap = (int64_t)std::min({c->nodes.bytes / sizeof(NodeRec), c->msum.bytes / 32, c->meta.bytes});
   B.curve = c->opt.curve;
   B.any_empty = false;

@@ -32,6 +32,19 @@ struct alignas(16) NodeRec {
 };
 static_assert(sizeof(NodeRec) == 64, "node record must be 64 bytes");
 
+// What the moments pass reads of one cell, written by the level scatter in
+// position order (one coalesced record per cell instead of reads scattered
+// over the per-position arrays): the children's slots [c0, c0 + nc), the
+// cell's own slot and particle range, and its integer coordinates at its
+// geometric level (the level, or the chain cell's above a bucket) with that
+// level in bits 21-25 of cz_geo and bit 26 set for a bucket that is always
+// opened.
+struct alignas(16) CellRec {
+  int32_t c0, nc, slot, first, count;
+  uint32_t cx, cy, cz_geo;
+};
+static_assert(sizeof(CellRec) == 32, "cell record must be 32 bytes");
+
 // Per-system geometry in device memory (first/count from the host, the root
 // cube from the build).
 struct SysInfo {
@@ -199,7 +212,7 @@ struct bh_ctx {
   bh::DevBuf far_slot;          // int32 per far-pool entry: node slot of a cell entry, -1 a particle
   bh::DevBuf meta;              // int8 [slots] 32 * kind + level (inspection only)
   bh::DevBuf levels;            // int32 level counts, offsets and cursors (3 x 24)
-  bh::DevBuf lcells;            // int32 cells grouped by level
+  bh::DevBuf lcells;            // CellRec cells grouped by level
   bh::DevBuf gflag;             // int32 group start flags
   bh::DevBuf gidx;              // int32 exclusive scan of the flags (group index)
   bh::DevBuf glen;              // int32 group length at its start position
@@ -300,7 +313,7 @@ struct TreeBuffers {
   int curve;              // key order: 0 Morton, 1 Peano-Hilbert
   bool any_empty;         // some system holds no particle (its root record is written apart)
   int32_t *lcount, *loff, *lcursor;  // cells per level: counts, offsets [23], scatter cursors
-  int32_t *lcells;                   // cell owner positions grouped by level
+  CellRec *lcells;                   // cell records grouped by level
   int64_t slot_cap;       // capacity of nodes/msum/meta in slots
   uint64_t *sorted_keys;  // out: the buffer holding the sorted keys
 };

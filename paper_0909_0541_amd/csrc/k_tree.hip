@@ -410,6 +410,45 @@ __device__ __forceinline__ unsigned long long level_peers(int l) {
 
 constexpr int kLevelTile = 16;  // positions per thread in the level kernels
 
+// The moments pass's record of the cell owned at position j (level lev).
+__device__ __forceinline__ CellRec cell_record(int j, int lev, const int8_t *__restrict__ level,
+                                               const int32_t *__restrict__ cparent, const int32_t *__restrict__ cslot,
+                                               const int32_t *__restrict__ cfc, const int32_t *__restrict__ nchild,
+                                               const int32_t *__restrict__ cfirst, const int32_t *__restrict__ ccount,
+                                               const double *__restrict__ spos, const SysInfo *__restrict__ sys,
+                                               int nsys) {
+  CellRec r;
+  r.c0 = nsys + cfc[j];
+  r.nc = nchild[j];
+  r.slot = cslot[j];
+  r.first = cfirst[j];
+  r.count = ccount[j];
+  // A bucket (level 21) is opened unless a chain of single-child cells sits
+  // above it: the opening bound shrinks down a chain (theta < 2/sqrt(3)), so
+  // the chain is accepted iff its deepest cell, at level 20, is; the bucket
+  // then carries that cell's side and s.
+  int geo = lev;
+  bool always_open = false;
+  if (lev == kKeyLevels) {
+    const int P = cparent[j];
+    const int lp = (P < 0) ? -1 : (int)level[P];
+    if (lp < kKeyLevels - 1) geo = kKeyLevels - 1;
+    else always_open = true;
+  }
+  // The cell's coordinates at level geo: the top geo bits of each quantised
+  // coordinate of any of its members (a cell of either curve is one aligned
+  // cube, a bucket one point), here the particle at the owning position,
+  // which lies in the cell.
+  const SysInfo &S = sys[system_of(sys, nsys, j)];
+  uint32_t q[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) q[k] = quantise(spos[3 * (int64_t)j + k], S.lo[k], S.scale) >> (kKeyLevels - geo);
+  r.cx = q[0];
+  r.cy = q[1];
+  r.cz_geo = q[2] | ((uint32_t)geo << 21) | (always_open ? (1u << 26) : 0u);
+  return r;
+}
+
 __global__ __launch_bounds__(256) void k_level_count(const int8_t *__restrict__ level, int64_t n,
                                                      int32_t *__restrict__ lcount) {
   __shared__ int32_t c[kKeyLevels + 1];
@@ -433,8 +472,13 @@ __global__ __launch_bounds__(256) void k_level_count(const int8_t *__restrict__ 
 // level.
 __global__ __launch_bounds__(256) void k_level_scatter(const int8_t *__restrict__ level, int64_t n,
                                                        const int32_t *__restrict__ lcount, int32_t *__restrict__ loff,
-                                                       int32_t *__restrict__ lcursor, int32_t *__restrict__ lcells,
-                                                       DevInfo *info) {
+                                                       int32_t *__restrict__ lcursor, const int32_t *__restrict__ cparent,
+                                                       const int32_t *__restrict__ cslot, const int32_t *__restrict__ cfc,
+                                                       const int32_t *__restrict__ nchild,
+                                                       const int32_t *__restrict__ cfirst,
+                                                       const int32_t *__restrict__ ccount,
+                                                       const double *__restrict__ spos, const SysInfo *__restrict__ sys,
+                                                       int nsys, CellRec *__restrict__ lcells, DevInfo *info) {
   __shared__ int32_t c[kKeyLevels + 1], base[kKeyLevels + 1], off[kKeyLevels + 2];
   if (threadIdx.x <= kKeyLevels) c[threadIdx.x] = 0;
   if (threadIdx.x == 0) {
@@ -470,66 +514,75 @@ __global__ __launch_bounds__(256) void k_level_scatter(const int8_t *__restrict_
   __syncthreads();
   for (int q = 0; q < kLevelTile; ++q) {
     const int64_t j = b0 + (int64_t)q * blockDim.x + threadIdx.x;
-    if (l[q] >= 0) lcells[base[l[q]] + pos[q]] = (int32_t)j;
+    if (l[q] >= 0)
+      lcells[base[l[q]] + pos[q]] = cell_record((int)j, l[q], level, cparent, cslot, cfc, nchild, cfirst, ccount, spos,
+                                                sys, nsys);
   }
 }
 
-// Moments of the cells of one level from their children's raw sums.
-__global__ void k_moments(int lev, const int32_t *__restrict__ lcells, const int32_t *__restrict__ loff,
-                          const int8_t *__restrict__ level, const int32_t *__restrict__ cparent,
-                          const int32_t *__restrict__ cslot,
-                          const int32_t *__restrict__ cfc, const int32_t *__restrict__ nchild,
-                          const int32_t *__restrict__ cfirst, const int32_t *__restrict__ ccount,
-                          const double *__restrict__ spos, const SysInfo *__restrict__ sys, int nsys, int64_t n,
-                          int64_t cap, NodeRec *__restrict__ nodes, double *__restrict__ msum,
-                          double *__restrict__ qmom, float4 *__restrict__ qpack,
+// Moments of the cells of one level from their children's raw sums.  A
+// level's time is the latency of one cell's chain of reads: a cell reads its
+// record (written in position order by the level scatter), then its
+// children's sums, kMomChunk children at a time (indices clamped to the last
+// child, the extra values unused), before it adds any of them.  The sums add
+// the children in slot order starting from zero.
+constexpr int kMomChunk = 4;
+
+__global__ void k_moments(int lev, const CellRec *__restrict__ lcells, const int32_t *__restrict__ loff,
+                          const SysInfo *__restrict__ sys, int nsys, int64_t cap, NodeRec *__restrict__ nodes,
+                          double *__restrict__ msum, double *__restrict__ qmom, float4 *__restrict__ qpack,
                           int8_t *__restrict__ meta, DevInfo *info) {
   const int64_t end = loff[lev + 1];
+  // the system's frame: loaded once when there is one system
+  double slo[3] = {sys[0].lo[0], sys[0].lo[1], sys[0].lo[2]}, sside = sys[0].side;
   for (int64_t k = (int64_t)loff[lev] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < end;
        k += (int64_t)gridDim.x * blockDim.x) {
-  const int j = lcells[k];
-  const int c0 = nsys + cfc[j], nc = nchild[j];
-  if (c0 < 0 || nc < 0 || (int64_t)c0 + nc > cap || cslot[j] < 0 || cslot[j] >= cap) {
+  const CellRec cr = lcells[k];
+  const int c0 = cr.c0, nc = cr.nc, slot = cr.slot;
+  if (c0 < 0 || nc < 0 || (int64_t)c0 + nc > cap || slot < 0 || slot >= cap) {
     atomicOr(&info->err, kErrBuild);
     continue;
   }
-  double m = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
-  for (int ci = 0; ci < nc; ++ci) {
-    const double *q = msum + 4 * (int64_t)(c0 + ci);
-    m = __dadd_rn(m, q[0]);
-    mx = __dadd_rn(mx, q[1]);
-    my = __dadd_rn(my, q[2]);
-    mz = __dadd_rn(mz, q[3]);
+  if (nsys > 1) {
+    const SysInfo &S = sys[system_of(sys, nsys, cr.first)];
+    slo[0] = S.lo[0];
+    slo[1] = S.lo[1];
+    slo[2] = S.lo[2];
+    sside = S.side;
   }
-  const int slot = cslot[j];
+  double m = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
+  for (int cb = 0; cb < nc; cb += kMomChunk) {
+    double2 a[kMomChunk], b[kMomChunk];
+#pragma unroll
+    for (int u = 0; u < kMomChunk; ++u) {
+      const double2 *q = reinterpret_cast<const double2 *>(msum + 4 * (int64_t)(c0 + min(cb + u, nc - 1)));
+      a[u] = q[0];
+      b[u] = q[1];
+    }
+#pragma unroll
+    for (int u = 0; u < kMomChunk; ++u) {
+      if (cb + u < nc) {
+        m = __dadd_rn(m, a[u].x);
+        mx = __dadd_rn(mx, a[u].y);
+        my = __dadd_rn(my, b[u].x);
+        mz = __dadd_rn(mz, b[u].y);
+      }
+    }
+  }
   msum[4 * (int64_t)slot] = m;
   msum[4 * (int64_t)slot + 1] = mx;
   msum[4 * (int64_t)slot + 2] = my;
   msum[4 * (int64_t)slot + 3] = mz;
-  const SysInfo &S = sys[system_of(sys, nsys, j)];
-  // A bucket (level 21) is opened unless a chain of single-child cells sits
-  // above it: the opening bound shrinks down a chain (theta < 2/sqrt(3)), so
-  // the chain is accepted iff its deepest cell, at level 20, is; the bucket
-  // then carries that cell's side and s.
-  int geo = lev;
-  bool always_open = false;
-  if (lev == kKeyLevels) {
-    const int P = cparent[j];
-    const int lp = (P < 0) ? -1 : (int)level[P];
-    if (lp < kKeyLevels - 1) geo = kKeyLevels - 1;
-    else always_open = true;
-  }
-  const double l = ldexp(S.side, -geo);
-  // the cell's coordinates from its first member's (for either curve)
-  uint32_t q[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) q[k] = quantise(spos[3 * (int64_t)cfirst[j] + k], S.lo[k], S.scale);
+  const int geo = (int)((cr.cz_geo >> 21) & 31u);
+  const bool always_open = (cr.cz_geo >> 26) & 1u;
+  const double l = ldexp(sside, -geo);
+  const uint32_t q[3] = {cr.cx, cr.cy, cr.cz_geo & 0x1fffffu};
   double c[3], com[3];
   const double mv[3] = {mx, my, mz};
   for (int k = 0; k < 3; ++k) {
-    double h = (double)(q[k] >> (kKeyLevels - geo)) + 0.5;
+    double h = (double)q[k] + 0.5;
     h = __dmul_rn(h, l);
-    c[k] = __dadd_rn(S.lo[k], h);
+    c[k] = __dadd_rn(slo[k], h);
     com[k] = (m > 0.0) ? mv[k] / m : c[k];
   }
   const double dx = __dsub_rn(c[0], com[0]), dy = __dsub_rn(c[1], com[1]), dz = __dsub_rn(c[2], com[2]);
@@ -543,8 +596,8 @@ __global__ void k_moments(int lev, const int32_t *__restrict__ lcells, const int
   r.s = sqrt(d2);
   r.child = c0;
   r.nchild = nc;
-  r.first = cfirst[j];
-  r.count = ccount[j];
+  r.first = cr.first;
+  r.count = cr.count;
   nodes[slot] = r;
   if (qmom) {
     // second moments about the centre of mass from the children's own, each
@@ -627,14 +680,13 @@ void build_tree_device(TreeBuffers &B, hipStream_t s) {
                                          B.smass, n, nsys, B.slot_cap, B.cslot, B.nodes, B.msum, B.meta, B.info);
   if (B.any_empty) k_empty_roots<<<blocks_for(nsys), 256, 0, s>>>(B.sys, nsys, B.nodes, B.msum, B.meta);
   k_level_count<<<blocks_for(n, 256 * kLevelTile), 256, 0, s>>>(B.level, n, B.lcount);
-  k_level_scatter<<<blocks_for(n, 256 * kLevelTile), 256, 0, s>>>(B.level, n, B.lcount, B.loff, B.lcursor, B.lcells,
-                                                                   B.info);
+  k_level_scatter<<<blocks_for(n, 256 * kLevelTile), 256, 0, s>>>(B.level, n, B.lcount, B.loff, B.lcursor,
+                                                                   B.cparent, B.cslot, B.cfc, B.nchild, B.cfirst,
+                                                                   B.ccount, B.spos, B.sys, nsys, B.lcells, B.info);
   const unsigned mgrid = (unsigned)std::min<int64_t>(blocks_for(n), 512);
   for (int lev = kKeyLevels; lev >= 0; --lev)
-    k_moments<<<mgrid, 256, 0, s>>>(lev, B.lcells, B.loff, B.level, B.cparent,
-                                                                        B.cslot, B.cfc, B.nchild, B.cfirst, B.ccount,
-                                                                        B.spos, B.sys, nsys, n, B.slot_cap, B.nodes,
-                                                                        B.msum, B.qmom, B.qpack, B.meta, B.info);
+    k_moments<<<mgrid, 256, 0, s>>>(lev, B.lcells, B.loff, B.sys, nsys, B.slot_cap, B.nodes, B.msum, B.qmom, B.qpack,
+                                    B.meta, B.info);
 }
 
 }  // namespace bh
