@@ -95,7 +95,7 @@ typedef struct {
   double t_neighbor_ms;     /* bh_neighbors calls */
   int64_t neighbor_pairs;   /* last bh_neighbors: neighbours found (sum of the counts) */
   int64_t neighbor_tests;   /* last bh_neighbors: member-candidate pairs whose distance was tested */
-  double t_theta_ms;        /* bh_group_theta calls (features, probe walk, inference) */
+  double t_theta_ms;        /* bh_group_theta calls (features, probe walk, inference, walk order) */
   int32_t n_theta_calls;
   int32_t n_theta_fallback; /* last force call: groups whose per-group theta was NaN (walked with the
                                call's theta) */
@@ -374,6 +374,11 @@ bh_status bh_mlp_infer(bh_ctx *ctx, const bh_mlp *net, int64_t rows, const float
  * max(n, 1) values; pass it as theta_group to bh_compute_forces.  A row
  * whose network output is not a number gives theta NaN, which the force call
  * replaces by its own theta for that group (the fixed-theta fallback).
+ * The call also orders the list walk of the next force calls with a
+ * theta_group on these groups (until bh_make_groups): each eighth of the
+ * groups, the range one XCD's walk waves take, longest predicted walk first,
+ * from the features and theta.  The order changes only which wave walks a
+ * group and when, never a list or a result.
  * With timing enabled, stats.t_theta_ms sums these calls. */
 bh_status bh_group_theta(bh_ctx *ctx, const bh_mlp *net, const double *eps_sys, float shift, float *theta);
 

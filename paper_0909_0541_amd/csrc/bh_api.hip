@@ -402,7 +402,7 @@ void bh_destroy(bh_ctx *c) {
                     &c->hist, &c->nodes, &c->msum, &c->meta, &c->levels, &c->lcells, &c->gflag, &c->gidx, &c->glen, &c->ginfo, &c->gbox, &c->glist,
                     &c->gmass, &c->bbox_part, &c->sys, &c->par, &c->info, &c->direct_part, &c->energy_part,
                     &c->glists, &c->far_pool, &c->near_pool, &c->far_next, &c->near_next,
-                    &c->items, &c->feps, &c->mlp_work, &c->mlp_feat, &c->pp_next, &c->order_hist, &c->tasks, &c->ranges, &c->segs,
+                    &c->items, &c->feps, &c->mlp_work, &c->mlp_feat, &c->pp_next, &c->order_hist, &c->walk_order, &c->walk_order_hist, &c->tasks, &c->ranges, &c->segs,
                     &c->split_ctr, &c->gsplit, &c->gnseg, &c->gsegfirst, &c->skeys[0], &c->skeys[1], &c->svals[0],
                     &c->svals[1], &c->shist, &c->sscan, &c->srows, &c->spbase, &c->sgroups, &c->psum,
                     &c->qmom, &c->qpack, &c->far_slot, &c->walk_hist};
@@ -507,6 +507,7 @@ bh_status bh_make_groups(bh_ctx *c, int32_t n_crit, int64_t *n_groups_out) {
   c->n_crit = n_crit;
   c->have_groups = true;
   c->have_forces = false;
+  c->walk_order_valid = false;
   if (n_groups_out) {
     st = check_device_errors(c);
     if (st) return st;
@@ -653,6 +654,7 @@ static bh_status forces_common(bh_ctx *c, const double *eps_sys, const double *t
     W.gsplit = P<int32_t>(c->gsplit);
     W.visit_cap = visit_cap;
     W.mean_list = auto_split ? P<int32_t>(c->walk_hist) : nullptr;
+    W.order = (theta_group && c->walk_order_valid) ? P<int32_t>(c->walk_order) : nullptr;
     W.wait_ticks = c->wait_ticks;
     reset_list_counters(P<DevInfo>(c->info), c->stream);
     split_reset(W.ctr, P<DevInfo>(c->info), W.tasks, c->task_cap, c->stream);
@@ -1143,6 +1145,17 @@ static bh_status theta_common(bh_ctx *c, const bh_mlp *net, const double *eps_sy
   // rows = -1: the kernel reads the group count on the device
   mlp_infer_device(net->params, net->mu, net->sigma, P<float>(c->mlp_feat), -1, cap, P<DevInfo>(c->info), shift,
                    theta, c->stream);
+  // the list walk's order for these groups, from their features and theta
+  st = ensure(c, c->walk_order, sizeof(int32_t) * (size_t)cap, "walk order");
+  if (st) return st;
+  if (!c->walk_order_hist.p) {
+    st = ensure(c, c->walk_order_hist, order_hist_bytes(), "walk order bins");
+    if (st) return st;
+    order_clear_device(P<int32_t>(c->walk_order_hist), c->stream);  // every later call leaves it zero
+  }
+  walk_order_device(P<float>(c->mlp_feat), theta, P<DevInfo>(c->info), cap, P<int32_t>(c->walk_order_hist),
+                    P<int32_t>(c->walk_order), c->stream);
+  c->walk_order_valid = true;
   st = timer_stop(c, c->t_theta);
   if (st) return st;
   return hip_check(c, hipGetLastError(), "kernel launch (inference)");

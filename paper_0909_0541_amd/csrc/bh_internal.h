@@ -177,6 +177,7 @@ struct bh_ctx {
   bool have_tree = false;
   bool have_groups = false;
   bool xq_clean = false;  // the per-XCD group queues are known to be 0 (reset by make_groups, used by walks)
+  bool walk_order_valid = false;  // walk_order holds a permutation of the current groups (bh_group_theta)
   bool have_forces = false;
   bool have_quad = false;  // the current tree carries second moments
   bool have_neighbors = false;  // a neighbour search ran since the last build
@@ -238,6 +239,8 @@ struct bh_ctx {
   bh::DevBuf mlp_feat;          // FP32 [n][12] features of bh_group_theta
   bh::DevBuf pp_next;           // int32 per slot: thread pointers of the per-particle walk
   bh::DevBuf order_hist;        // int32 cost bins of the queue orders
+  bh::DevBuf walk_order;        // int32 [n] order in which the list walk takes the groups (learned theta)
+  bh::DevBuf walk_order_hist;   // int32 cost bins of the walk order (zero between calls)
   bh::DevBuf walk_hist;         // int32 [4]: mean list length of the last force call (automatic split cap)
   // split walks: tasks (ping-pong), range pool, segments, counters, per-group
   // flags, segment sort and partial sums
@@ -371,6 +374,8 @@ struct WalkListArgs {
   int seg_cap;
   long long wait_ticks;      // wall-clock ticks a wave may wait for a task
   int32_t *gsplit;           // per group: 1 when its list is in segments
+  const int32_t *order;      // nullable: the groups in the order the walk takes them; each eighth of
+                             // [0, G) a permutation of itself (walk_order_device)
 };
 void walk_lists_device(const WalkListArgs &a, int grid, hipStream_t s);
 // k_neighbors.hip: neighbour search and SPH density over the groups
@@ -473,6 +478,12 @@ void force_lists_device(const ForceArgs &a, int grid, hipStream_t s);
 void item_order_device(const ForceArgs &f, const int32_t *gsplit, const int32_t *gnseg, int64_t gcap, int32_t *hist,
                        int32_t *mean_list, int32_t *items, hipStream_t s);
 void order_clear_device(int32_t *hist, hipStream_t s);
+// Walk order of a learned-theta step (k_order.hip): within each eighth of
+// the groups, the groups by predicted walk time from their features (FP32
+// [cap][12]) and theta, longest first; hist holds order_hist_bytes() and is
+// zero on entry (every call leaves it zero).
+void walk_order_device(const float *feat, const float *theta, const DevInfo *info, int64_t cap, int32_t *hist,
+                       int32_t *order, hipStream_t s);
 int force_lists_blocks_per_cu(bool quad);
 void reset_list_counters(DevInfo *info, hipStream_t s);
 

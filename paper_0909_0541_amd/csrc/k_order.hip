@@ -169,6 +169,90 @@ __global__ __launch_bounds__(256) void k_order_scatter(ForceArgs f, const int32_
   }
 }
 
+// Walk order of a learned-theta step.  The list walk takes the groups of
+// each eighth of [0, G) on one XCD (Morton order keeps neighbouring walks on
+// one L2), and a launch ends with the walks taken last: a long walk taken
+// late holds the launch open while the other waves idle.  With the
+// features at hand, the groups of each eighth are taken longest first by a
+// predicted walk time: log2 t = sum_k w_k f_k + w_theta log2(theta) + w_0
+// (t in microseconds under a full launch), the weights a least-squares fit
+// to the measured walk time of every group of the clustered 2M and 4M
+// boxes (correlation 0.79 and 0.83 with the measured times), binned in
+// 1/32 octaves.  The order changes which wave walks which group and when,
+// never a group's list.
+constexpr float kWalkW[BH_MLP_FEATURES] = {0.1395f, 0.1570f, -0.0535f, -0.1039f, 0.0227f, -0.1509f,
+                                           0.0256f, 0.2257f,  -0.0245f, 0.2982f,  0.1105f, 0.0308f};
+constexpr float kWalkWTheta = -1.5131f, kWalkW0 = 0.4690f;
+
+__device__ __forceinline__ int eighth_of(int64_t G, int g) {
+  int x = 0;
+#pragma unroll
+  for (int k = 1; k < kXcd; ++k) x += (g >= (int)(G * k / kXcd)) ? 1 : 0;
+  return x;
+}
+
+// (XCD, bin) key of group g: its eighth, then longest first.
+__device__ __forceinline__ int walk_key(const float *__restrict__ feat, const float *__restrict__ theta, int64_t G,
+                                        int g) {
+  float p = kWalkW0;
+#pragma unroll
+  for (int k = 0; k < BH_MLP_FEATURES; ++k) p = fmaf(kWalkW[k], feat[(int64_t)BH_MLP_FEATURES * g + k], p);
+  p = fmaf(kWalkWTheta, __log2f(theta[g]), p);
+  p = fminf(fmaxf(p, 0.0f), 15.99f);  // (a NaN, from a theta <= 0 or a NaN feature, goes to bin 0)
+  const int bin = (int)(p * 32.0f);
+  return eighth_of(G, g) * kBins + (kBins - 1 - bin);
+}
+
+__global__ __launch_bounds__(256) void k_worder_hist(const float *__restrict__ feat, const float *__restrict__ theta,
+                                                     const DevInfo *__restrict__ info, int64_t cap,
+                                                     int32_t *__restrict__ hist) {
+  __shared__ int32_t h[kKeys];
+  const int64_t G = min<int64_t>(info->n_groups, cap);
+  const int64_t t0 = (int64_t)blockIdx.x * kTile;
+  if (t0 >= G) return;
+  for (int b = threadIdx.x; b < kKeys; b += blockDim.x) h[b] = 0;
+  __syncthreads();
+  for (int64_t g = t0 + threadIdx.x; g < G && g < t0 + kTile; g += blockDim.x)
+    atomicAdd(&h[walk_key(feat, theta, G, (int)g)], 1);
+  __syncthreads();
+  for (int b = threadIdx.x; b < kKeys; b += blockDim.x)
+    if (h[b]) atomicAdd(&hist[b], h[b]);
+}
+
+// Each group takes a place from its key's cursor (the order within a key is
+// that of the atomics, which changes no result).
+__global__ __launch_bounds__(256) void k_worder_scatter(const float *__restrict__ feat,
+                                                        const float *__restrict__ theta,
+                                                        const DevInfo *__restrict__ info, int64_t cap,
+                                                        int32_t *__restrict__ cursor, int32_t *__restrict__ order) {
+  constexpr int kPer = kTile / 256;
+  __shared__ int32_t cnt[kKeys], base[kKeys];
+  const int64_t G = min<int64_t>(info->n_groups, cap);
+  const int64_t t0 = (int64_t)blockIdx.x * kTile;
+  if (t0 >= G) return;
+  for (int b = threadIdx.x; b < kKeys; b += blockDim.x) cnt[b] = 0;
+  __syncthreads();
+  int key[kPer], rank[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int64_t g = t0 + j * 256 + threadIdx.x;
+    key[j] = -1;
+    if (g < G) {
+      key[j] = walk_key(feat, theta, G, (int)g);
+      rank[j] = atomicAdd(&cnt[key[j]], 1);
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kKeys; b += blockDim.x) base[b] = cnt[b] ? atomicAdd(&cursor[b], cnt[b]) : 0;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    if (key[j] < 0) continue;
+    const int64_t p = (int64_t)base[key[j]] + rank[j];
+    if (p >= 0 && p < G) order[p] = (int)(t0 + j * 256 + threadIdx.x);
+  }
+}
+
 }  // namespace
 
 size_t order_hist_bytes() { return sizeof(int32_t) * (2 * kKeys + 16); }
@@ -183,6 +267,20 @@ void item_order_device(const ForceArgs &f, const int32_t *gsplit, const int32_t 
   k_order_hist<<<grid, 256, 0, s>>>(f, gsplit, gnseg, gcap, hist);
   k_order_scan<<<1, 1024, 0, s>>>(hist, cursor, xstart, f.info, mean_list);
   k_order_scatter<<<grid, 256, 0, s>>>(f, gsplit, gnseg, gcap, cursor, items);
+}
+
+}  // namespace bh
+
+namespace bh {
+
+void walk_order_device(const float *feat, const float *theta, const DevInfo *info, int64_t cap, int32_t *hist,
+                       int32_t *order, hipStream_t s) {
+  if (cap <= 0) return;
+  const unsigned grid = (unsigned)((cap + kTile - 1) / kTile);
+  int32_t *cursor = hist + kKeys, *xstart = hist + 2 * kKeys;
+  k_worder_hist<<<grid, 256, 0, s>>>(feat, theta, info, cap, hist);
+  k_order_scan<<<1, 1024, 0, s>>>(hist, cursor, xstart, info, nullptr);
+  k_worder_scatter<<<grid, 256, 0, s>>>(feat, theta, info, cap, cursor, order);
 }
 
 }  // namespace bh

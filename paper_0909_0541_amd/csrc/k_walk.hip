@@ -156,7 +156,9 @@ __device__ __forceinline__ int wait_slot(const WalkListArgs &a, int t, int lane)
 // Morton order from eight contiguous eighths, one per XCD (workgroups go to
 // the XCDs round robin), so that the waves sharing an L2 walk neighbouring
 // groups and read mostly the same nodes; a wave whose eighth is done takes
-// from the others.
+// from the others.  With an order (learned theta), the q-th group taken from
+// an eighth is the q-th of that eighth in the order: longest predicted walk
+// first, so that the walks taken last are short ones.
 template <bool SPLIT>
 __device__ __forceinline__ int next_unit(const WalkListArgs &a, int G, int xcd, int &tried, int &ticket, bool &waiter,
                                          int &task, int lane) {
@@ -183,6 +185,13 @@ __device__ __forceinline__ int next_unit(const WalkListArgs &a, int G, int xcd, 
         const int q = take_one(&a.info->xq[x * kLineInts], lane);
         if (s0 + q < s1) {
           g = s0 + q;
+          if (a.order) {
+            // the eighth's groups in the given order (a value outside the
+            // eighth is reported and the Morton place taken instead)
+            const int o = __builtin_amdgcn_readfirstlane(a.order[s0 + q]);
+            if (o >= s0 && o < s1) g = o;
+            else if (lane == 0) atomicOr(&a.info->err, kErrStack);
+          }
           break;
         }
         ++tried;

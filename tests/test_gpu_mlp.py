@@ -220,3 +220,30 @@ def test_group_theta_and_forces_with_learned_theta(gpu):
     t.groups(n_crit)
     ref = t.forces(eps, 0.6, theta_g=thv)
     check_forces(acc.cpu().numpy().astype(np.float64), pot.cpu().numpy().astype(np.float64), ref)
+
+
+def test_walk_order_changes_no_result(gpu):
+    """group_theta also orders the list walk (each eighth of the groups by
+    predicted walk time, longest first); a new make_groups on the same tree
+    drops that order, so the second walk takes the groups in Morton order.
+    Both walks must build the same lists: the same forces bit for bit."""
+    bh = gpu
+    from paper_0909_0541_amd import learned
+    net = learned.ThetaNet.load(learned.DEFAULT_NET)
+    pos, mass = inputs.clustered(60000, 21, n_halos=50)[:2]
+    eps, n_crit = 1e-4, 64
+    c = bh.Context()
+    c.build_tree(to_dev(pos), to_dev(mass))
+    G = c.make_groups(n_crit)
+    assert G >= 64
+    th = c.group_theta(net.params, net.mu, net.sigma, eps)
+    tg = th[:G].contiguous()
+    acc1, pot1 = c.compute_forces(eps, 0.6, theta_group=tg)
+    s1 = c.get_stats()
+    assert s1.error_flags == 0
+    assert c.make_groups(n_crit) == G
+    acc2, pot2 = c.compute_forces(eps, 0.6, theta_group=tg)
+    s2 = c.get_stats()
+    assert s2.error_flags == 0
+    assert s1.interactions == s2.interactions and s1.list_entries == s2.list_entries
+    assert torch.equal(acc1, acc2) and torch.equal(pot1, pot2)
