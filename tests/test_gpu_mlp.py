@@ -247,3 +247,32 @@ def test_walk_order_changes_no_result(gpu):
     assert s2.error_flags == 0
     assert s1.interactions == s2.interactions and s1.list_entries == s2.list_entries
     assert torch.equal(acc1, acc2) and torch.equal(pot1, pot2)
+
+
+def test_walk_order_in_batched_split_walks(gpu):
+    """The same with several systems and split walks: with a fixed visit cap
+    both walks split the same groups into the same keyed segments, so the
+    ordered walk's forces equal the Morton-order walk's bit for bit."""
+    bh = gpu
+    from paper_0909_0541_amd import learned
+    net = learned.ThetaNet.load(learned.DEFAULT_NET)
+    sizes = [30000, 5000, 1, 20000, 12000]
+    parts = [inputs.clustered(k, 40 + i, n_halos=max(1, k // 1000))[:2] for i, k in enumerate(sizes)]
+    pos = np.concatenate([p for p, _ in parts])
+    mass = np.concatenate([m for _, m in parts])
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    eps = [1e-4] * len(sizes)
+    c = bh.Context(split_visits=256)
+    c.build_batch(off, to_dev(pos), to_dev(mass))
+    G = c.make_groups(32)
+    th = c.group_theta(net.params, net.mu, net.sigma, eps)
+    tg = th[:G].contiguous()
+    acc1, pot1 = c.compute_forces_batch(eps, [0.6] * len(sizes), theta_group=tg)
+    s1 = c.get_stats()
+    assert s1.error_flags == 0 and s1.n_split_groups > 0
+    assert c.make_groups(32) == G
+    acc2, pot2 = c.compute_forces_batch(eps, [0.6] * len(sizes), theta_group=tg)
+    s2 = c.get_stats()
+    assert s2.error_flags == 0 and s2.n_split_groups == s1.n_split_groups
+    assert s1.interactions == s2.interactions
+    assert torch.equal(acc1, acc2) and torch.equal(pot1, pot2)
