@@ -112,8 +112,8 @@ typedef struct {
                             by several waves; tasks 5 hand-overs deep walk to the end (0:
                             default, automatic: a single system is not split (its walk then
                             runs without the split machinery, which is faster); a batch
-                            splits at 48 per particle of a walk wave, i.e.
-                            48 n / (CUs x walk waves per CU), at least 12288, and at least 4
+                            splits at 16 per particle of a walk wave, i.e.
+                            16 n / (CUs x walk waves per CU), at least 12288, and at least 4
                             times the mean list length of the previous force call on the
                             context, so that only outlier walks split; -1: never; else
                             >= 64, exactly).  Results do not depend on when or where the

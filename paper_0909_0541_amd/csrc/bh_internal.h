@@ -134,7 +134,7 @@ struct Segment {
 };
 constexpr int kSplitDepth = 5;       // tasks this many hand-overs deep walk to the end
 constexpr int kSplitVisits = 12288;  // smallest default node tests before a walk hands over
-constexpr int kSplitPerParticle = 48;  // default cap: this many node tests per particle of a walk wave
+constexpr int kSplitPerParticle = 16;  // default cap: this many node tests per particle of a walk wave
 constexpr int kSplitMeanFactor = 4;    // and at least this many times the previous walk's mean list length
 constexpr int kDonateTasks = 16;     // tasks made from one handed-over stack
 struct SplitCounters {               // device

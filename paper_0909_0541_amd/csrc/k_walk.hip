@@ -41,7 +41,7 @@ namespace {
 constexpr int kStack = 1024;      // range stack entries
 constexpr int kReserve = 8 * 24;  // growth bound of the stack in one-range mode
 constexpr int kTaskStack = 512;   // largest first stack of a task
-constexpr int kWaiters = 64;      // waves that wait for tasks once the groups are taken
+constexpr int kWaiters = 256;     // waves that wait for tasks once the groups are taken
 constexpr int kProbeStack = 512;  // range stack of the probe walk (its theta = 1 lists are short)
 
 __device__ __forceinline__ double norm3(double a, double b, double c) {
