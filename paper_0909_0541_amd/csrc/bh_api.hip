@@ -217,6 +217,7 @@ static bh_status ensure_particles(bh_ctx *c, int64_t n, int nsys) {
       {&c->keys[0], 8 * N, "keys"},       {&c->keys[1], 8 * N, "keys"},
       {&c->vals[0], 4 * N, "vals"},       {&c->vals[1], 4 * N, "vals"},
       {&c->sys_in, 4 * N, "sys_in"},      {&c->spos, 24 * N, "spos"},
+      {&c->pmass, sizeof(PosMass) * N, "packed positions"},
       {&c->smass, 8 * N, "smass"},        {&c->perm, 4 * N, "perm"},
       {&c->delta, N, "delta"},            {&c->level, N, "level"},
       {&c->cdigit, N, "cdigit"},          {&c->pdigit, N, "pdigit"},
@@ -303,6 +304,7 @@ static bh_status build_common(bh_ctx *c, int32_t nsys, const int64_t *offsets, c
   B.bbox_part = P<double>(c->bbox_part);
   B.spos = P<double>(c->spos);
   B.smass = P<double>(c->smass);
+  B.pm = P<PosMass>(c->pmass);
   B.perm = P<int32_t>(c->perm);
   B.delta = P<int8_t>(c->delta);
   B.level = P<int8_t>(c->level);
@@ -402,7 +404,7 @@ void bh_destroy(bh_ctx *c) {
                     &c->hist, &c->nodes, &c->msum, &c->meta, &c->levels, &c->lcells, &c->gflag, &c->gidx, &c->glen, &c->ginfo, &c->gbox, &c->glist,
                     &c->gmass, &c->bbox_part, &c->sys, &c->par, &c->info, &c->direct_part, &c->energy_part,
                     &c->glists, &c->far_pool, &c->near_pool, &c->far_next, &c->near_next,
-                    &c->items, &c->feps, &c->mlp_work, &c->mlp_feat, &c->pp_next, &c->order_hist, &c->walk_order, &c->walk_order_hist, &c->tasks, &c->ranges, &c->segs,
+                    &c->items, &c->pmass, &c->feps, &c->mlp_work, &c->mlp_feat, &c->pp_next, &c->order_hist, &c->walk_order, &c->walk_order_hist, &c->tasks, &c->ranges, &c->segs,
                     &c->split_ctr, &c->gsplit, &c->gnseg, &c->gsegfirst, &c->skeys[0], &c->skeys[1], &c->svals[0],
                     &c->svals[1], &c->shist, &c->sscan, &c->srows, &c->spbase, &c->sgroups, &c->psum,
                     &c->qmom, &c->qpack, &c->far_slot, &c->walk_hist};

@@ -45,6 +45,13 @@ struct alignas(16) CellRec {
 };
 static_assert(sizeof(CellRec) == 32, "cell record must be 32 bytes");
 
+// A particle's position and mass in input order, packed by the key pass so
+// that the gather into key order reads one aligned 32-byte record per
+// particle rather than two scattered reads.
+struct alignas(32) PosMass {
+  double x, y, z, m;
+};
+
 // Per-system geometry in device memory (first/count from the host, the root
 // cube from the build).
 struct SysInfo {
@@ -191,6 +198,7 @@ struct bh_ctx {
   bh::DevBuf keys[2], vals[2];  // u64 keys, u32 values (radix sort ping-pong)
   bh::DevBuf sys_in;            // int32 system of each input row
   bh::DevBuf spos, smass;       // FP64 sorted positions [n][3] and masses
+  bh::DevBuf pmass;             // PosMass [n] in input order (build scratch)
   bh::DevBuf perm;              // int32 sorted -> input row
   bh::DevBuf delta;             // int8 common-digit count of neighbours
   bh::DevBuf owner;             // int32 owner position of each split (or bucket run start)
@@ -305,6 +313,7 @@ struct TreeBuffers {
   void *scan_tmp;
   double *bbox_part;
   double *spos, *smass;
+  PosMass *pm;      // input positions and masses, packed by the key pass
   int32_t *perm;
   int8_t *delta, *level, *cdigit, *pdigit;
   int32_t *owner, *cfirst, *ccount, *cparent, *pparent, *mask, *nchild, *cfc, *cslot;

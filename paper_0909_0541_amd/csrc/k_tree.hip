@@ -160,18 +160,26 @@ __device__ __forceinline__ void hilbert_transpose(uint32_t (&x)[3]) {
 
 __global__ void k_keys(const double *__restrict__ pos, const double *__restrict__ mass, int64_t n,
                        const int32_t *__restrict__ sys_in, const SysInfo *__restrict__ sys, int curve,
-                       uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, DevInfo *info) {
+                       uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, PosMass *__restrict__ pm,
+                       DevInfo *info) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const SysInfo &S = sys[sys_in ? sys_in[i] : 0];
+  const double x[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
   uint32_t q[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) q[k] = quantise(pos[3 * i + k], S.lo[k], S.scale);
+  for (int k = 0; k < 3; ++k) q[k] = quantise(x[k], S.lo[k], S.scale);
   if (curve) hilbert_transpose(q);
   // x bit is the most significant of each octal digit
   keys[i] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
   vals[i] = (uint32_t)i;
-  double m = mass[i];
+  const double m = mass[i];
+  PosMass r;
+  r.x = x[0];
+  r.y = x[1];
+  r.z = x[2];
+  r.m = m;
+  pm[i] = r;
   if (!(m >= 0.0) || !isfinite(m)) atomicOr(&info->err, kErrBadMass);
 }
 
@@ -180,7 +188,7 @@ __global__ void k_keys(const double *__restrict__ pos, const double *__restrict_
 // octant masks cleared for the topology pass and the level counters for the
 // level pass.
 __global__ void k_gather(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
-                         const double *__restrict__ pos, const double *__restrict__ mass, int64_t n,
+                         const PosMass *__restrict__ pm, int64_t n,
                          const int32_t *__restrict__ sys_in, double *__restrict__ spos, double *__restrict__ smass,
                          int32_t *__restrict__ perm, int8_t *__restrict__ delta, int32_t *__restrict__ mask,
                          int32_t *__restrict__ lcount) {
@@ -190,10 +198,11 @@ __global__ void k_gather(const uint64_t *__restrict__ keys, const uint32_t *__re
   if (i >= n) return;
   uint32_t j = vals[i];
   perm[i] = (int32_t)j;
-  spos[3 * i] = pos[3 * (int64_t)j];
-  spos[3 * i + 1] = pos[3 * (int64_t)j + 1];
-  spos[3 * i + 2] = pos[3 * (int64_t)j + 2];
-  smass[i] = mass[j];
+  const PosMass r = pm[j];
+  spos[3 * i] = r.x;
+  spos[3 * i + 1] = r.y;
+  spos[3 * i + 2] = r.z;
+  smass[i] = r.m;
   int d = -1;
   if (i + 1 < n) {
     const bool same = sys_in ? (sys_in[j] == sys_in[vals[i + 1]]) : true;
@@ -657,7 +666,7 @@ void build_tree_device(TreeBuffers &B, hipStream_t s) {
   }
   if (nsys > 1) k_system_of_input<<<blocks_for(n), 256, 0, s>>>(B.sys, nsys, n, B.sys_in);
   k_keys<<<blocks_for(n), 256, 0, s>>>(B.pos, B.mass, n, nsys > 1 ? B.sys_in : nullptr, B.sys, B.curve, B.keys[0],
-                                        B.vals[0], B.info);
+                                        B.vals[0], B.pm, B.info);
   int cur = radix_sort_pairs(B.keys[0], B.keys[1], B.vals[0], B.vals[1], n, 0, 64, B.hist, B.scan_tmp,
                              &B.info->err, s);
   if (nsys > 1) {
@@ -667,7 +676,7 @@ void build_tree_device(TreeBuffers &B, hipStream_t s) {
   }
   const uint64_t *keys = B.keys[cur];
   B.sorted_keys = B.keys[cur];
-  k_gather<<<blocks_for(n), 256, 0, s>>>(keys, B.vals[cur], B.pos, B.mass, n, nsys > 1 ? B.sys_in : nullptr, B.spos,
+  k_gather<<<blocks_for(n), 256, 0, s>>>(keys, B.vals[cur], B.pm, n, nsys > 1 ? B.sys_in : nullptr, B.spos,
                                           B.smass, B.perm, B.delta, B.mask, B.lcount);
   k_owner<<<blocks_for(n), 256, 0, s>>>(keys, B.delta, n, B.sys, nsys, B.owner, B.level, B.cfirst, B.ccount);
   k_cells<<<blocks_for(n), 256, 0, s>>>(keys, B.delta, B.owner, B.level, n, B.sys, nsys, B.cfirst, B.ccount,
