@@ -259,34 +259,58 @@ __global__ void k_owner(const uint64_t *__restrict__ keys, const int8_t *__restr
   }
 }
 
+// bit into mask[P] for every active lane of the wave, with one atomic per
+// run of neighbouring lanes that share P (neighbouring positions mostly
+// share a parent; an OR is the same whatever the grouping).  Every lane of
+// the wave must call it.
+__device__ __forceinline__ void or_into_parent(int32_t *__restrict__ mask, int P, int bit, bool active) {
+  const int lane = lane_id();
+  const int key = active ? P : -1;
+  // (every lane takes part in the shuffles: a lane left out of one gives 0)
+  const int prev = __shfl_up(key, 1, kWave), next = __shfl_down(key, 1, kWave);
+  const bool head = lane == 0 || prev != key;
+  const int run = __popcll(__ballot(head) & ((2ull << lane) - 1ull));
+  int v = active ? bit : 0;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int u = __shfl_up(v, d, kWave);
+    const int r = __shfl_up(run, d, kWave);
+    if (lane >= d && r == run) v |= u;
+  }
+  const bool tail = lane == kWave - 1 || next != key;
+  if (active && tail && v) atomicOr(&mask[P], v);
+}
+
 // Parent and octant of every owned cell; octant masks of the parents.
 __global__ void k_cells(const uint64_t *__restrict__ keys, const int8_t *__restrict__ delta,
                         const int32_t *__restrict__ owner, const int8_t *__restrict__ level, int64_t n,
                         const SysInfo *__restrict__ sys, int nsys, const int32_t *__restrict__ cfirst,
                         const int32_t *__restrict__ ccount, int32_t *__restrict__ cparent, int8_t *__restrict__ cdigit,
                         int32_t *__restrict__ mask, DevInfo *info) {
-  int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (jj >= n) return;
+  const int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int j = (int)jj;
-  const int l = level[j];
-  if (l < 0) return;
-  const int s = system_of(sys, nsys, j);
-  const int lo = sys[s].first;
-  const int a = cfirst[j], b = a + ccount[j] - 1;
-  const int dl = (a > lo) ? delta[a - 1] : -1;
-  const int dr = delta[b];
-  const int lp = max(dl, dr);
-  if (lp < 0) {
-    cparent[j] = -1 - s;
-    cdigit[j] = 0;
-  } else {
-    const int sp = (dl == lp) ? a - 1 : b;
-    const int P = owner[sp];
-    const int dg = key_digit(keys[a], lp + 1);
-    cparent[j] = P;
-    cdigit[j] = (int8_t)dg;
-    atomicOr(&mask[P], 1 << dg);
+  const int l = (jj < n) ? level[j] : -1;
+  int P = -1, bit = 0;
+  if (l >= 0) {
+    const int s = system_of(sys, nsys, j);
+    const int lo = sys[s].first;
+    const int a = cfirst[j], b = a + ccount[j] - 1;
+    const int dl = (a > lo) ? delta[a - 1] : -1;
+    const int dr = delta[b];
+    const int lp = max(dl, dr);
+    if (lp < 0) {
+      cparent[j] = -1 - s;
+      cdigit[j] = 0;
+    } else {
+      const int sp = (dl == lp) ? a - 1 : b;
+      P = owner[sp];
+      const int dg = key_digit(keys[a], lp + 1);
+      cparent[j] = P;
+      cdigit[j] = (int8_t)dg;
+      bit = 1 << dg;
+    }
   }
+  or_into_parent(mask, P, bit, P >= 0);
 }
 
 // Parent of every particle: a cell (octant mask updated), a bucket, or none
@@ -295,29 +319,32 @@ __global__ void k_particle_parents(const uint64_t *__restrict__ keys, const int8
                                    const int32_t *__restrict__ owner, int64_t n, const SysInfo *__restrict__ sys,
                                    int nsys, int32_t *__restrict__ pparent, int8_t *__restrict__ pdigit,
                                    int32_t *__restrict__ mask) {
-  int64_t ii = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (ii >= n) return;
+  const int64_t ii = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int i = (int)ii;
-  const int s = system_of(sys, nsys, i);
-  const int lo = sys[s].first;
-  const int dl = (i > lo) ? delta[i - 1] : -1;
-  const int dr = delta[i];
-  const int lp = max(dl, dr);
-  if (lp < 0) {
-    pparent[i] = -1 - s;
-    pdigit[i] = 0;
-    return;
+  int P = -1, bit = 0;
+  if (ii < n) {
+    const int s = system_of(sys, nsys, i);
+    const int lo = sys[s].first;
+    const int dl = (i > lo) ? delta[i - 1] : -1;
+    const int dr = delta[i];
+    const int lp = max(dl, dr);
+    if (lp < 0) {
+      pparent[i] = -1 - s;
+      pdigit[i] = 0;
+    } else {
+      const int sp = (dl == lp) ? i - 1 : i;
+      P = owner[sp];
+      pparent[i] = P;
+      if (lp == kKeyLevels) {
+        pdigit[i] = 0;  // bucket member: slot order is Morton order
+      } else {
+        const int dg = key_digit(keys[i], lp + 1);
+        pdigit[i] = (int8_t)dg;
+        bit = 1 << dg;
+      }
+    }
   }
-  const int sp = (dl == lp) ? i - 1 : i;
-  const int P = owner[sp];
-  pparent[i] = P;
-  if (lp == kKeyLevels) {
-    pdigit[i] = 0;  // bucket member: slot order is Morton order
-  } else {
-    const int dg = key_digit(keys[i], lp + 1);
-    pdigit[i] = (int8_t)dg;
-    atomicOr(&mask[P], 1 << dg);
-  }
+  or_into_parent(mask, P, bit, bit != 0);
 }
 
 __global__ void k_nchild(const int8_t *__restrict__ level, const int32_t *__restrict__ mask,
