@@ -57,13 +57,13 @@ HELDOUT_SEED = 54321            # a second judge sample, not used by any calibra
 # was taken on.
 TRAFFIC = {
     # clustered box, 4,194,304 particles, theta 0.3328125 (the 1e-3 RMS theta):
-    # FETCH_SIZE 5474038.9 KiB x 1.99986 (a 512 MiB device copy reads as
-    # 262161.75 KiB) + WRITE_SIZE 284474.5 KiB x 1.0 (the copy writes 524288 KiB)
-    "clustered_4m": {"theta": 0.3328125, "bytes_per_launch": 11501374540,
+    # FETCH_SIZE 5469209.5 KiB x 1.99986 (a 512 MiB device copy reads as
+    # 262162.06 KiB) + WRITE_SIZE 284460.4 KiB x 1.0 (the copy writes 524288 KiB)
+    "clustered_4m": {"theta": 0.3328125, "bytes_per_launch": 11491456847,
                      "k_force_sha256": "93ad7855e81c3498b4bc5c04c38bd65053f45409b516eb9112de6d482a5281a9"},
     # clustered box, 2,097,152 particles, theta 0.41997070312499996:
-    # FETCH_SIZE 1650132.1 KiB x 1.99986 + WRITE_SIZE 146715.0 KiB x 1.0
-    "clustered_2m": {"theta": 0.41997070312499996, "bytes_per_launch": 3529477123,
+    # FETCH_SIZE 1651514.0 KiB x 1.99986 + WRITE_SIZE 146739.9 KiB x 1.0
+    "clustered_2m": {"theta": 0.41997070312499996, "bytes_per_launch": 3532333361,
                      "k_force_sha256": "93ad7855e81c3498b4bc5c04c38bd65053f45409b516eb9112de6d482a5281a9"},
 }
 
